@@ -1,0 +1,197 @@
+"""Seeded synthetic workloads: parameters and initial fields.
+
+This module holds no step arithmetic.  It only builds the analytic initial
+conditions of the paper's benchmarks (tanh interface profiles,
+eq:equilibrium_profile; prescribed vortex velocity, Sec. 4.1) and parameter
+sets, as plain numbers and float64 numpy arrays.  Both the HIP library (through
+its binding) and the CPU oracle consume the same arrays.
+
+Node (i, j) sits at x = i, y = j (lattice units); arrays are indexed [j, i].
+Phase +1 is the heavy liquid (rho1), phase -1 the light gas (rho2); a droplet
+has phi > 0 inside, a bubble phi < 0 inside.
+"""
+
+import dataclasses
+import math
+
+import numpy as np
+
+TAU_F = 0.5 + math.sqrt(3.0) / 6.0
+
+
+def base_params(nx, ny, **kw):
+    p = dict(nx=nx, ny=ny, wall_x=False, wall_y=False, coupled=True,
+             rho1=1.0, rho2=1.0, mu1=0.1, mu2=0.1, sigma=1e-3, W=4.0, M=0.02,
+             lam=0.005, tau_f=TAU_F, gx=0.0, gy=0.0, rho_ref=0.0,
+             filter_n=11, filter_a=0.5, compact=False, compact_n=5,
+             compact_alpha=0.45, K=2, eps=1e-9)
+    p.update(kw)
+    return p
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    params: dict
+    phi0: np.ndarray
+    ux0: np.ndarray
+    uy0: np.ndarray
+    p0: np.ndarray
+    steps: int
+    meta: dict = dataclasses.field(default_factory=dict)
+
+
+def _grid(nx, ny):
+    y, x = np.meshgrid(np.arange(ny, dtype=np.float64), np.arange(nx, dtype=np.float64),
+                       indexing="ij")
+    return x, y
+
+
+def drop_field(nx, ny, xc, yc, R, W, inside=1.0, periodic=True):
+    """tanh(2(R - r)/W) (inside = +1) or tanh(2(r - R)/W) (inside = -1)."""
+    x, y = _grid(nx, ny)
+    dx = x - xc
+    dy = y - yc
+    if periodic:
+        dx = dx - nx * np.round(dx / nx)
+        dy = dy - ny * np.round(dy / ny)
+    r = np.sqrt(dx * dx + dy * dy)
+    return np.tanh(inside * 2.0 * (R - r) / W)
+
+
+def vortex_velocity(nx, ny, U):
+    """u = -U sin^2(pi x) sin(2 pi y), v = U sin^2(pi y) sin(2 pi x), x = i/L, y = j/L."""
+    x, y = _grid(nx, ny)
+    xs = x / nx
+    ys = y / ny
+    ux = -U * np.sin(np.pi * xs) ** 2 * np.sin(2 * np.pi * ys)
+    uy = U * np.sin(np.pi * ys) ** 2 * np.sin(2 * np.pi * xs)
+    return ux, uy
+
+
+def vortex(n=128, U=0.05, steps=1000):
+    """Single-vortex deformation of a circle (Sec. 4.1): CH-only, periodic."""
+    R = 0.15 * n
+    phi = drop_field(n, n, 0.5 * n, 0.75 * n, R, 4.0, inside=1.0)
+    ux, uy = vortex_velocity(n, n, U)
+    prm = base_params(n, n, coupled=False, sigma=1e-3, lam=0.05, filter_n=0)
+    return Workload("vortex", prm, phi, ux, uy, np.zeros_like(phi), steps,
+                    dict(R=R, U=U))
+
+
+def droplet(n=200, seed=0, steps=20000, sigma=0.01, radii=(20, 25, 30, 35, 40)):
+    """Stationary droplet (Laplace law, Sec. 4.3): density ratio 1000, viscosity ratio 100."""
+    rng = np.random.default_rng(seed)
+    R = float(rng.choice(np.asarray(radii, dtype=np.float64)))
+    c = np.array([n / 2, n / 2]) + rng.uniform(-2.0, 2.0, 2)
+    phi = drop_field(n, n, c[0], c[1], R, 4.0, inside=1.0)
+    z = np.zeros_like(phi)
+    prm = base_params(n, n, rho1=1.0, rho2=1e-3, mu1=0.01, mu2=1e-4, sigma=sigma)
+    return Workload("droplet", prm, phi, z, z.copy(), z.copy(), steps,
+                    dict(R=R, xc=float(c[0]), yc=float(c[1])))
+
+
+def capillary(nx=128, ny=512, steps=50000, A0_frac=0.01, nu=1e-3, sigma=1e-3,
+              rho1=1.0, rho2=1e-3):
+    """Capillary wave (Sec. 4.4): heavy layer below, walls in y, periodic in x."""
+    x, y = _grid(nx, ny)
+    A0 = A0_frac * nx
+    y0 = ny / 2 + A0 * np.cos(2 * np.pi * x / nx)
+    phi = np.tanh(2.0 * (y0 - y) / 4.0)
+    z = np.zeros_like(phi)
+    prm = base_params(nx, ny, wall_y=True, rho1=rho1, rho2=rho2, mu1=nu * rho1,
+                      mu2=nu * rho2, sigma=sigma)
+    return Workload("capillary", prm, phi, z, z.copy(), z.copy(), steps,
+                    dict(A0=A0, y0=ny / 2, nu=nu))
+
+
+def place_bubbles(n, nb, rmin, rmax, W, rng, max_tries=200000):
+    """Non-overlapping random circles on a periodic n x n box (min-image distance
+    >= R_i + R_j + 2W)."""
+    out = []
+    tries = 0
+    while len(out) < nb:
+        tries += 1
+        if tries > max_tries:
+            raise RuntimeError("could not place bubbles")
+        R = rng.uniform(rmin, rmax)
+        c = rng.uniform(0, n, 2)
+        ok = True
+        for (cx, cy, Rj) in out:
+            dx = c[0] - cx
+            dy = c[1] - cy
+            dx -= n * round(dx / n)
+            dy -= n * round(dy / n)
+            if math.hypot(dx, dy) < R + Rj + 2 * W:
+                ok = False
+                break
+        if ok:
+            out.append((float(c[0]), float(c[1]), float(R)))
+    return out
+
+
+def bubbles_field(n, bubbles, W):
+    """phi0 = min_i tanh(2(d_i - R_i)/W); evaluated in a box around each bubble
+    (beyond d - R > 12 W the tanh rounds to exactly 1.0 in float64)."""
+    phi = np.ones((n, n), dtype=np.float64)
+    for (cx, cy, R) in bubbles:
+        h = int(math.ceil(R + 12 * W)) + 1
+        xs = np.arange(int(math.floor(cx)) - h, int(math.floor(cx)) + h + 1)
+        ys = np.arange(int(math.floor(cy)) - h, int(math.floor(cy)) + h + 1)
+        X, Y = np.meshgrid(xs.astype(np.float64), ys.astype(np.float64), indexing="xy")
+        d = np.sqrt((X - cx) ** 2 + (Y - cy) ** 2)
+        v = np.tanh(2.0 * (d - R) / W)
+        iy = np.mod(ys, n)[:, None]
+        ix = np.mod(xs, n)[None, :]
+        phi[iy, ix] = np.minimum(phi[iy, ix], v)
+    return phi
+
+
+def bubble_ensemble(n=4096, nb=200, seed=0, steps=2000, rmin=10.0, rmax=60.0,
+                    Eo=10.0, Re=35.0, R_ref=35.0, U_g=0.005):
+    """Throughput ensemble: gas bubbles in liquid on a periodic box, density ratio
+    1000, viscosity ratio 100; gravity from Eo and Re at the reference radius
+    (U_g = sqrt(2 g R), Eo = 2 rho1 U_g^2 R / sigma, Re = rho1 U_g 2R / mu1, Sec. 4.5)."""
+    rng = np.random.default_rng(seed)
+    W = 4.0
+    bl = place_bubbles(n, nb, rmin, rmax, W, rng)
+    phi = bubbles_field(n, bl, W)
+    rho1, rho2 = 1.0, 1e-3
+    g = U_g * U_g / (2.0 * R_ref)
+    sigma = 2.0 * rho1 * U_g * U_g * R_ref / Eo
+    mu1 = rho1 * U_g * 2.0 * R_ref / Re
+    pm = float(phi.mean())
+    rho_ref = rho1 * (1 + pm) / 2 + rho2 * (1 - pm) / 2
+    z = np.zeros_like(phi)
+    prm = base_params(n, n, rho1=rho1, rho2=rho2, mu1=mu1, mu2=mu1 / 100.0,
+                      sigma=sigma, gy=-g, rho_ref=rho_ref)
+    return Workload("bubbles", prm, phi, z, z.copy(), z.copy(), steps,
+                    dict(nb=nb, bubbles=bl, g=g))
+
+
+def rising_bubble(nx=256, ny=1024, R=32.0, xc=128.0, yc=128.0, sigma=1e-3, Eo=10.0,
+                  Re=35.0, steps=4000, sigma_ref=1e-3):
+    """Rising bubble in a closed box (walls on all sides), Sec. 4.5 set-up;
+    g and viscosities fixed from Eo and Re at sigma_ref."""
+    rho1, rho2 = 1.0, 1e-3
+    g = Eo * sigma_ref / (4.0 * rho1 * R * R)
+    U_g = math.sqrt(2.0 * g * R)
+    mu1 = rho1 * U_g * 2.0 * R / Re
+    phi = drop_field(nx, ny, xc, yc, R, 4.0, inside=-1.0, periodic=False)
+    z = np.zeros_like(phi)
+    prm = base_params(nx, ny, wall_x=True, wall_y=True, rho1=rho1, rho2=rho2,
+                      mu1=mu1, mu2=mu1 / 100.0, sigma=sigma, gy=-g, rho_ref=0.0)
+    return Workload("rising", prm, phi, z, z.copy(), z.copy(), steps, dict(g=g))
+
+
+def random_smooth(nx, ny, seed, amp=1.0, modes=4):
+    """A smooth random periodic field (sum of a few Fourier modes), for tests."""
+    rng = np.random.default_rng(seed)
+    x, y = _grid(nx, ny)
+    f = np.zeros((ny, nx))
+    for _ in range(modes):
+        kx = rng.integers(0, 4)
+        ky = rng.integers(0, 4)
+        ph = rng.uniform(0, 2 * np.pi)
+        f += rng.uniform(-1, 1) * np.cos(2 * np.pi * (kx * x / nx + ky * y / ny) + ph)
+    return amp * f / modes

@@ -69,7 +69,7 @@ from typing import Optional
 import torch
 
 from .lattice import C, W, OPP, M as MRT, MM_DIAG_INV, FILTER_D
-from .ops import ext, crop, iso_grad, iso_lap, d4x, d4y, selective_filter, CS2_INV
+from .ops import ext, crop, iso_grad, iso_lap, d4x, d4y, selective_filter, sqrt
 from . import compact
 
 DT = torch.float64
@@ -306,7 +306,7 @@ def fd_rhs(phi, prm):
     Mx = d4x(mu)                                       # halo 2
     My = d4y(mu)
     ph = crop(P, 5, 2)
-    mag = torch.sqrt((Gx * Gx + Gy * Gy) + prm.eps * prm.eps)
+    mag = sqrt((Gx * Gx + Gy * Gy) + prm.eps * prm.eps)
     nx_ = Gx / mag
     ny_ = Gy / mag
     cW = 2 * (1 - ph * ph) / prm.W

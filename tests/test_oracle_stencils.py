@@ -174,3 +174,23 @@ def test_compact_wall_symmetry_and_transfer_in_interior():
     w = np.sin(np.pi * 3 * (i + 0.5) / n)          # odd about the walls
     out = compact.lowpass(torch.tensor(w)[None, :], 1, N, alpha, wall=True, odd=True)[0].numpy()
     assert np.allclose(out, T * w, atol=1e-13)
+
+
+def test_sqrt_is_correctly_rounded():
+    """The oracle's sqrt returns the double nearest to the exact square root
+    (checked with exact rational arithmetic on random and extreme inputs)."""
+    from fractions import Fraction
+    rng = np.random.default_rng(11)
+    xs = np.concatenate([rng.uniform(0, 1, 3000), np.exp(rng.normal(0, 30, 3000)),
+                         1e-18 + rng.uniform(0, 1e-17, 1000), [0.0, 1.0, 4.0, 1e-300, 2.0]])
+    ys = ops.sqrt(torch.tensor(xs)).numpy()
+    for x, y in zip(xs, ys):
+        X = Fraction(float(x))
+        s = Fraction(float(y))
+        up = Fraction(float(np.nextafter(y, np.inf)))
+        dn = Fraction(float(np.nextafter(y, -np.inf))) if y > 0 else -s
+        assert ((s + dn) / 2) ** 2 <= X <= ((s + up) / 2) ** 2, x
+    # differentiable: d sqrt(x)/dx = 1/(2 sqrt x)
+    t = torch.tensor([0.25, 4.0], dtype=torch.float64, requires_grad=True)
+    ops.sqrt(t).sum().backward()
+    assert torch.allclose(t.grad, torch.tensor([1.0, 0.25], dtype=torch.float64))

@@ -1,0 +1,161 @@
+/*
+ * lbm2p -- C ABI of the MI355X (gfx950) library for the fractional-step MRT
+ * lattice Boltzmann method for two-phase flow with large density ratios
+ * (Zhang, Guo & Li, arXiv:1812.02459).
+ *
+ * One call to lbm2p_step advances the whole D2Q9 lattice by one time step:
+ *   1. streaming of the CH populations f and the pressure populations g and
+ *      their moments phi_bar = sum f (eq:compute_phi), p = c_s^2 sum g (Eq:p),
+ *      j = sum g c (Eq:u);
+ *   2. the finite-difference sub-step of the split CH equation (eq:step2) with
+ *      the interfacial-profile and flux corrections (eq:final_mCHE), TVD-RK3
+ *      in time (eq:TVD-3order) and fourth-order central differences
+ *      (eq:fourOrder_FDM);
+ *   3. the velocity of Eq:u with the force F = F_p + F_s + F_nu + F_m + F_g
+ *      (eq:reformNS, eq:surfaceforce) on the isotropic stencils of
+ *      eq:dicretized, solved by K fixed-point iterations;
+ *   4. the selective filter of (p, u) (eq:filter, App. B) or the compact
+ *      (tridiagonal) variant;
+ *   5. the MRT collision of f (eq:distribution_CH, eq:feq_CH, eq:Fi) and g
+ *      (eq:distribution_NS, eq:geq, eq:Gi) with Lambda = M^-1 S M
+ *      (eq:collison, eq:D2Q9MRT).
+ * In CH-only mode (coupled = 0) steps 3-4 are skipped and the velocity is a
+ * prescribed field (Sec. 4.1, 4.2).
+ *
+ * Conventions.
+ *  - Every field crossing the ABI is a float64 plane [ny][nx], row-major
+ *    (x fastest), in DEVICE memory owned by the caller.  The library keeps
+ *    its own state in its precision (FP64 or FP32) inside the workspace.
+ *  - The caller owns the workspace (device memory, >= lbm2p_workspace_bytes)
+ *    and the HIP stream; the library allocates no device memory.  Pointers
+ *    are borrowed for the duration of a call only (the workspace for the
+ *    life of the context).
+ *  - All calls enqueue work on the context's stream and return without
+ *    waiting, except lbm2p_volume and lbm2p_profile_read, which synchronise
+ *    the stream.  One context per stream; contexts share no state.
+ *  - Every function returns LBM2P_OK (0) or an error code; no exception or
+ *    abort crosses the ABI.  lbm2p_strerror names a code.
+ */
+#ifndef LBM2P_H
+#define LBM2P_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LBM2P_OK = 0,
+  LBM2P_EINVAL = 1,      /* invalid argument or parameter                  */
+  LBM2P_ENOSPACE = 2,    /* workspace smaller than lbm2p_workspace_bytes   */
+  LBM2P_EHIP = 3,        /* a HIP runtime call failed                      */
+  LBM2P_ENONFINITE = 4,  /* a diagnostic found NaN or Inf in the state     */
+  LBM2P_ESTATE = 5       /* call out of order (e.g. step before init)      */
+};
+
+/* Parameters.  Phase phi = +1 has density rho1 and dynamic viscosity mu1,
+ * phase phi = -1 has rho2, mu2 (eq:rho, eq:dynamic_vis).  Lattice units,
+ * dx = dt = 1 (Sec. 3.1). */
+typedef struct lbm2p_params {
+  int32_t nx, ny;          /* lattice size, each >= 16                         */
+  int32_t wall_x, wall_y;  /* 0 periodic, 1 no-slip walls half-way outside the
+                              first/last node (bounce-back, mirror ghosts)     */
+  int32_t coupled;         /* 1 NS + CH; 0 CH only with a prescribed velocity  */
+  int32_t precision;       /* 0 FP64; 1 FP32 state and arithmetic (FP64
+                              diagnostics)                                     */
+  double rho1, rho2, mu1, mu2;
+  double sigma;            /* surface tension: kappa = 3 sigma W / 8,
+                              beta = 3 sigma / (4 W)  (Sec. 2.1)               */
+  double W;                /* interface width                                  */
+  double M;                /* mobility; eta = M / (c_s^2 (tau_f - 1/2))
+                              (eq:mobility)                                    */
+  double lam;              /* lambda: J_d = lambda J_phi + q                   */
+  double tau_f;            /* CH relaxation time: s_3^f = s_5^f = 1/tau_f      */
+  double gx, gy;           /* gravity; F_g = (rho - rho_ref) g                 */
+  double rho_ref;
+  int32_t filter_n;        /* explicit filter SF-n, n in {5,7,9,11}; 0 = off   */
+  int32_t compact;         /* 1 = compact tridiagonal filter instead           */
+  int32_t compact_n;       /* compact filter right-hand-side half width, 1..5  */
+  int32_t K;               /* fixed-point iterations of Eq:u, 1..8             */
+  double filter_a;         /* filter intensity a (eq:filter), 0..1             */
+  double compact_alpha;    /* compact filter alpha, (-1/2, 1/2)                */
+  double s_f[9];           /* MRT rates of f; entries 3 and 5 are set to 1/tau_f */
+  double s_g[9];           /* MRT rates of g; entries 7, 8 are 1/tau_g(x)      */
+  double eps;              /* regularisation of |grad phi| in n, >= 0          */
+  int32_t original_ch;     /* 1 = no FD sub-step (the original convective CH)  */
+  int32_t reserved;        /* must be 0                                        */
+} lbm2p_params;
+
+typedef struct lbm2p_ctx lbm2p_ctx;
+
+/* Device workspace size the context needs for these parameters.
+ * Returns EINVAL for invalid parameters (see lbm2p_create). */
+int lbm2p_workspace_bytes(const lbm2p_params* p, size_t* bytes);
+
+/* Create a context.  d_workspace: device memory of >= `bytes` bytes, aligned to
+ * 256 bytes, owned by the caller and kept alive until lbm2p_destroy.  stream:
+ * a hipStream_t (NULL = default stream).  Errors: EINVAL for nx, ny < 16,
+ * rho <= 0, mu < 0, W <= 0, M < 0, tau_f <= 1/2, any s outside [0, 2], a filter
+ * order not in {0,5,7,9,11}, compact_n outside 1..5, |compact_alpha| >= 1/2,
+ * K outside 1..8, filter_a outside [0,1], eps < 0, a wall axis shorter than the
+ * ghost depth; ENOSPACE for a small workspace; EHIP if an event cannot be made. */
+int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes,
+                 void* stream, lbm2p_ctx** out);
+
+/* Initial state (equilibrium populations, eq:feq_CH / eq:geq with
+ * mu = mu_phi(phi0), eq:chemical): f* = f^eq(phi0, mu, u0), g* = g^eq(p0, u0),
+ * u~ = u0.  Device float64 planes [ny][nx]; d_ux0/d_uy0/d_p0 may be NULL
+ * (zeros).  In CH-only mode (u0x, u0y) is the prescribed velocity for every
+ * later step. */
+int lbm2p_init_fields(lbm2p_ctx* c, const double* d_phi0, const double* d_ux0,
+                      const double* d_uy0, const double* d_p0);
+
+/* Advance n >= 0 time steps (asynchronous). ESTATE before init. */
+int lbm2p_step(lbm2p_ctx* c, int32_t n);
+
+/* Copy the current macroscopic fields to device float64 planes: phi^{n}
+ * (after the FD sub-step), the filtered velocity u~ and pressure p~ (kinematic,
+ * Sec. 2.2) and rho(clamp(phi)) (eq:rho).  Any pointer may be NULL. */
+int lbm2p_moments(lbm2p_ctx* c, double* d_phi, double* d_ux, double* d_uy,
+                  double* d_p, double* d_rho);
+
+/* Intermediate fields of the last step, one float64 plane:
+ *  0 phi_bar  1 p (raw, c_s^2 sum g)  2 j_x  3 j_y  4 u_x after the K
+ *  iterations  5 u_y after the K iterations  6 phi^(1)  7 phi^(2). */
+int lbm2p_fields(lbm2p_ctx* c, int32_t which, double* d_out);
+
+/* Diagnostics in FP64 (synchronises the stream), host array out[6]:
+ *  out[0] #{phi > 0} (volume, Sec. 4.3)  out[1] sum phi  out[2] sum p~
+ *  out[3] max |u~|  out[4] min phi  out[5] max phi.
+ * Returns ENONFINITE if sum phi or max|u~| is not finite. */
+int lbm2p_volume(lbm2p_ctx* c, double out[6]);
+
+/* State in canonical order (post-collision f*_i(x), g*_i(x), then u~), as
+ * device float64 arrays: d_f [9][ny][nx], d_g [9][ny][nx] (ignored in CH-only
+ * mode, may be NULL), d_u [2][ny][nx].  set_state makes a context resume from
+ * such a state. */
+int lbm2p_get_state(lbm2p_ctx* c, double* d_f, double* d_g, double* d_u);
+int lbm2p_set_state(lbm2p_ctx* c, const double* d_f, const double* d_g,
+                    const double* d_u);
+
+/* Kernel timing with HIP events on the context's stream.  lbm2p_profile(c, k)
+ * starts recording every launch of pass k (0 gather, 1 FD stage, 2 velocity
+ * iteration, 3 filter, 4 collide; -1 stops) for up to 65536 launches;
+ * lbm2p_profile_read synchronises and returns the summed milliseconds and the
+ * number of launches recorded since lbm2p_profile. */
+int lbm2p_profile(lbm2p_ctx* c, int32_t pass);
+int lbm2p_profile_read(lbm2p_ctx* c, double* ms, int64_t* launches);
+
+/* Release the context (not the workspace or the stream). */
+void lbm2p_destroy(lbm2p_ctx* c);
+
+/* Static string naming an error code. */
+const char* lbm2p_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM2P_H */

@@ -1,0 +1,266 @@
+// Pointwise and stencil arithmetic of the fractional-step MRT-LBM
+// (arXiv:1812.02459), device side.
+//
+// Every expression is written with a fixed evaluation order and the library is
+// compiled with -ffp-contract=off, so the FP64 path rounds exactly as the
+// written formula does.  Divisions by c_s^2 = 1/3 are multiplications by 3,
+// divisions by c_s^4 multiplications by 9 (exact constants).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lbm2p {
+
+// eq:D2Q9: c_0 = 0, c_1..4 = axes counter-clockwise from +x, c_5..8 diagonals.
+__host__ __device__ constexpr int cx_of(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+// opposite directions, written out: 1<->3, 2<->4, 5<->7, 6<->8
+__host__ __device__ constexpr int opp(int i) {
+  return i == 1 ? 3 : i == 2 ? 4 : i == 3 ? 1 : i == 4 ? 2 :
+         i == 5 ? 7 : i == 6 ? 8 : i == 7 ? 5 : i == 8 ? 6 : 0;
+}
+// weights: 4/9, 1/9 (axes), 1/36 (diagonals)
+__host__ __device__ constexpr double w_of(int i) {
+  return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+// eq:D2Q9MRT
+__host__ __device__ constexpr int mrt(int k, int j) {
+  constexpr int Mt[9][9] = {
+      {1, 1, 1, 1, 1, 1, 1, 1, 1},
+      {-4, -1, -1, -1, -1, 2, 2, 2, 2},
+      {4, -2, -2, -2, -2, 1, 1, 1, 1},
+      {0, 1, 0, -1, 0, 1, -1, -1, 1},
+      {0, -2, 0, 2, 0, 1, -1, -1, 1},
+      {0, 0, 1, 0, -1, 1, 1, -1, -1},
+      {0, 0, -2, 0, 2, 1, 1, -1, -1},
+      {0, 1, -1, 1, -1, 0, 0, 0, 0},
+      {0, 0, 0, 0, 0, 1, -1, 1, -1}};
+  return Mt[k][j];
+}
+// 1 / (M M^T)_kk: the rows of M are orthogonal with squared norms 9,36,36,6,12,6,12,4,4
+__host__ __device__ constexpr double mm_inv(int k) {
+  return k == 0 ? 1.0 / 9.0 : k == 1 || k == 2 ? 1.0 / 36.0 : k == 3 || k == 5 ? 1.0 / 6.0
+         : k == 4 || k == 6 ? 1.0 / 12.0 : 1.0 / 4.0;
+}
+
+// c_i . a, zero components skipped (c entries are 0 or +-1)
+template <typename T>
+__device__ __forceinline__ T cdot(int i, T ax, T ay) {
+  const int cx = cx_of(i), cy = cy_of(i);
+  if (cx == 0 && cy == 0) return T(0);
+  if (cy == 0) return cx > 0 ? ax : -ax;
+  if (cx == 0) return cy > 0 ? ay : -ay;
+  return (cx > 0 ? ax : -ax) + (cy > 0 ? ay : -ay);
+}
+
+// m = M v, sums in column order starting from the first non-zero entry
+template <typename T>
+__device__ __forceinline__ void m_apply(const T v[9], T m[9]) {
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int c = mrt(k, j);
+      if (c == 0) continue;
+      const T t = c == 1 ? v[j] : c == -1 ? -v[j] : T(c) * v[j];
+      acc = first ? t : acc + t;
+      first = false;
+    }
+    m[k] = acc;
+  }
+}
+
+// v = M^{-1} m = M^T diag(1/(M M^T)_kk) m
+template <typename T>
+__device__ __forceinline__ void minv_apply(const T m[9], T v[9]) {
+  T sc[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) sc[k] = m[k] * T(mm_inv(k));
+#pragma unroll
+  for (int j = 0; j < 9; ++j) {
+    T acc = T(0);
+    bool first = true;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int c = mrt(k, j);
+      if (c == 0) continue;
+      const T t = c == 1 ? sc[k] : c == -1 ? -sc[k] : T(c) * sc[k];
+      acc = first ? t : acc + t;
+      first = false;
+    }
+    v[j] = acc;
+  }
+}
+
+// eq:distribution_CH / eq:distribution_NS collision with Lambda = M^-1 S M:
+//   f* = f + M^{-1} [ (I - S/2) M F - S M (f - f^eq) ]       (in place on f)
+template <typename T>
+__device__ __forceinline__ void mrt_collide(T f[9], const T feq[9], const T F[9], const T s[9]) {
+  T d[9], md[9], mF[9], r[9], corr[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) d[i] = f[i] - feq[i];
+  m_apply(d, md);
+  m_apply(F, mF);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r[k] = (T(1) - s[k] * T(0.5)) * mF[k] - s[k] * md[k];
+  minv_apply(r, corr);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = f[i] + corr[i];
+}
+
+// eq:feq_CH
+template <typename T>
+__device__ __forceinline__ void f_eq(T phi, T mu, T ux, T uy, T eta, T feq[9]) {
+  const T usq = ux * ux + uy * uy;
+  feq[0] = (phi + ((T(w_of(0)) - T(1)) * eta) * mu) - ((T(w_of(0)) * phi) * usq) * T(1.5);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const T cu = cdot(i, ux, uy);
+    const T inner = ((cu * T(3)) + ((cu * cu) * T(4.5))) - usq * T(1.5);
+    feq[i] = (T(w_of(i)) * eta) * mu + (T(w_of(i)) * phi) * inner;
+  }
+}
+
+// eq:geq (velocity-based)
+template <typename T>
+__device__ __forceinline__ void g_eq(T p, T ux, T uy, T geq[9]) {
+  const T usq = ux * ux + uy * uy;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T cu = cdot(i, ux, uy);
+    geq[i] = T(w_of(i)) * (((p * T(3) + cu * T(3)) + (cu * cu) * T(4.5)) - usq * T(1.5));
+  }
+}
+
+// eq:Fi: F_i = w_i phi c_i.a / c_s^2
+template <typename T>
+__device__ __forceinline__ void src_f(T phi, T ax, T ay, T F[9]) {
+  F[0] = T(0);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) F[i] = ((T(w_of(i)) * phi) * cdot(i, ax, ay)) * T(3);
+}
+
+// eq:Gi with b = F/rho - grad p:
+//   G_i = w_i [ c_i.F / (rho c_s^2) + ((c_i.u)(c_i.b) - c_s^2 u.b) / c_s^4 ]
+template <typename T>
+__device__ __forceinline__ void src_g(T Fx, T Fy, T rho, T ux, T uy, T bx, T by, T G[9]) {
+  const T ub = ux * bx + uy * by;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T cF = cdot(i, Fx, Fy);
+    const T cu = cdot(i, ux, uy);
+    const T cb = cdot(i, bx, by);
+    G[i] = T(w_of(i)) * ((cF * T(3)) / rho + ((cu * cb) - ub / T(3)) * T(9));
+  }
+}
+
+// ----------------------------------------------------------------- stencils
+// A view of an LDS tile: element (x, y) of the tile's node frame sits at
+// a[(y + h) * w + (x + h)], h being the tile array's halo.
+template <typename T>
+struct Tile {
+  T* a;
+  int w, h;
+  __device__ __forceinline__ T operator()(int x, int y) const { return a[(y + h) * w + (x + h)]; }
+  __device__ __forceinline__ T& at(int x, int y) const { return a[(y + h) * w + (x + h)]; }
+};
+
+// eq:dicretized, first line: sum_{i!=0} w_i c_i P(x + c_i) / c_s^2
+template <typename T, typename A>
+__device__ __forceinline__ void iso_grad(const A& P, int x, int y, T& gx, T& gy) {
+  const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+  const T p1 = P(x + 1, y), p2 = P(x, y + 1), p3 = P(x - 1, y), p4 = P(x, y - 1);
+  const T p5 = P(x + 1, y + 1), p6 = P(x - 1, y + 1), p7 = P(x - 1, y - 1), p8 = P(x + 1, y - 1);
+  T ax = w1 * p1;
+  ax = ax - w1 * p3;
+  ax = ax + w2 * p5;
+  ax = ax - w2 * p6;
+  ax = ax - w2 * p7;
+  ax = ax + w2 * p8;
+  T ay = w1 * p2;
+  ay = ay - w1 * p4;
+  ay = ay + w2 * p5;
+  ay = ay + w2 * p6;
+  ay = ay - w2 * p7;
+  ay = ay - w2 * p8;
+  gx = ax * T(3);
+  gy = ay * T(3);
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ T iso_grad_x(const A& P, int x, int y) {
+  const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+  T ax = w1 * P(x + 1, y);
+  ax = ax - w1 * P(x - 1, y);
+  ax = ax + w2 * P(x + 1, y + 1);
+  ax = ax - w2 * P(x - 1, y + 1);
+  ax = ax - w2 * P(x - 1, y - 1);
+  ax = ax + w2 * P(x + 1, y - 1);
+  return ax * T(3);
+}
+
+template <typename T, typename A>
+__device__ __forceinline__ T iso_grad_y(const A& P, int x, int y) {
+  const T w1 = T(1.0 / 9.0), w2 = T(1.0 / 36.0);
+  T ay = w1 * P(x, y + 1);
+  ay = ay - w1 * P(x, y - 1);
+  ay = ay + w2 * P(x + 1, y + 1);
+  ay = ay + w2 * P(x - 1, y + 1);
+  ay = ay - w2 * P(x - 1, y - 1);
+  ay = ay - w2 * P(x + 1, y - 1);
+  return ay * T(3);
+}
+
+// eq:dicretized, second line: sum_{i!=0} 2 w_i (P(x + c_i) - P(x)) / c_s^2
+template <typename T, typename A>
+__device__ __forceinline__ T iso_lap(const A& P, int x, int y) {
+  const T a1 = T(2.0 * (1.0 / 9.0)), a2 = T(2.0 * (1.0 / 36.0));
+  const T p0 = P(x, y);
+  T acc = a1 * (P(x + 1, y) - p0);
+  acc = acc + a1 * (P(x, y + 1) - p0);
+  acc = acc + a1 * (P(x - 1, y) - p0);
+  acc = acc + a1 * (P(x, y - 1) - p0);
+  acc = acc + a2 * (P(x + 1, y + 1) - p0);
+  acc = acc + a2 * (P(x - 1, y + 1) - p0);
+  acc = acc + a2 * (P(x - 1, y - 1) - p0);
+  acc = acc + a2 * (P(x + 1, y - 1) - p0);
+  return acc * T(3);
+}
+
+// eq:chemical: mu = 4 beta (phi^3 - phi) - kappa lap(phi)
+template <typename T, typename A>
+__device__ __forceinline__ T chem_pot(const A& P, int x, int y, T c4b, T kappa) {
+  const T p0 = P(x, y);
+  return c4b * ((p0 * p0) * p0 - p0) - kappa * iso_lap<T>(P, x, y);
+}
+
+// eq:fourOrder_FDM: [P(-2) - 8 P(-1) + 8 P(+1) - P(+2)] / 12
+template <typename T>
+__device__ __forceinline__ T d4(T m2, T m1, T p1, T p2) {
+  return (((m2 - T(8) * m1) + T(8) * p1) - p2) / T(12);
+}
+
+// eq:rho and eq:dynamic_vis on clamp(phi, -1, 1); NaN passes through
+template <typename T>
+__device__ __forceinline__ T clamp1(T p) {
+  return p < T(-1) ? T(-1) : (p > T(1) ? T(1) : p);
+}
+template <typename T>
+__device__ __forceinline__ T density(T phi, T rho1, T rho2) {
+  const T c = clamp1(phi);
+  return (rho1 * (T(1) + c)) / T(2) + (rho2 * (T(1) - c)) / T(2);
+}
+template <typename T>
+__device__ __forceinline__ T kin_visc(T phi, T rho, T mu1, T mu2) {
+  const T c = clamp1(phi);
+  const T muv = (mu1 * (T(1) + c)) / T(2) + (mu2 * (T(1) - c)) / T(2);
+  return muv / rho;
+}
+
+}  // namespace lbm2p

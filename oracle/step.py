@@ -24,7 +24,13 @@ order its text implies):
 Readings (places where the paper is silent, ambiguous or garbled):
 R1  lambda (Sec. 4.2 "lambda in eq:final_mCHE", absent from it): J_d = lambda*J_phi + q.
 R2  n = grad phi/|grad phi| is regularised: |G|_eps = sqrt(|G|^2 + eps^2) in n
-    and in the first factor of J_phi.
+    and in the first factor of J_phi.  Where |G| < eps the correction is a
+    diffusion with coefficient lambda (1 - c/eps), c = 2(1 - phi^2)/W, so eps
+    sets how close to +-1 the bulk may sit before the term turns
+    anti-diffusive; eps = 1e-2 (2% of the interface gradient 2/W at W = 4)
+    keeps the sharpening inside the interface (|phi| < 0.99).  With
+    eps = 1e-9 the bulk of a light phase fills with grid-scale noise and 1000:1
+    gas bubbles diverge.
 R3  mu inside the FD sub-step uses the isotropic Laplacian of eq:dicretized;
     the first derivatives (grad phi, grad mu, divergence) use eq:fourOrder_FDM.
 R4  eq:fourOrder_FDM's typos (i+2dx, repeated y-2dy, j+dy) read as the standard
@@ -102,7 +108,7 @@ class Params:
     K: int = 2                    # velocity fixed-point iterations (R10)
     s_f: tuple = (1.0, 1.0, 1.0, None, 1.0, None, 1.0, 1.0, 1.0)
     s_g: tuple = (1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, None, None)
-    eps: float = 1e-9             # |grad phi| regularisation (R2)
+    eps: float = 1e-2             # |grad phi| regularisation (R2)
     original_ch: bool = False     # no FD sub-step: the original convective CH (Sec. 4.2)
 
     # derived constants, Sec. 2.1 and eq:mobility

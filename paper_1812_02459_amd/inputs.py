@@ -24,7 +24,7 @@ def base_params(nx, ny, **kw):
              rho1=1.0, rho2=1.0, mu1=0.1, mu2=0.1, sigma=1e-3, W=4.0, M=0.02,
              lam=0.005, tau_f=TAU_F, gx=0.0, gy=0.0, rho_ref=0.0,
              filter_n=11, filter_a=0.5, compact=False, compact_n=5,
-             compact_alpha=0.45, K=2, eps=1e-9)
+             compact_alpha=0.45, K=2, eps=1e-2)
     p.update(kw)
     return p
 
@@ -148,10 +148,15 @@ def bubbles_field(n, bubbles, W):
 
 
 def bubble_ensemble(n=4096, nb=200, seed=0, steps=2000, rmin=10.0, rmax=60.0,
-                    Eo=10.0, Re=35.0, R_ref=35.0, U_g=0.005):
+                    Eo=10.0, Re=35.0, R_ref=35.0, U_g=6.4e-4):
     """Throughput ensemble: gas bubbles in liquid on a periodic box, density ratio
     1000, viscosity ratio 100; gravity from Eo and Re at the reference radius
-    (U_g = sqrt(2 g R), Eo = 2 rho1 U_g^2 R / sigma, Re = rho1 U_g 2R / mu1, Sec. 4.5)."""
+    (U_g = sqrt(2 g R), Eo = 2 rho1 U_g^2 R / sigma, Re = rho1 U_g 2R / mu1, Sec. 4.5).
+
+    The lattice velocity scale U_g is free; 6.4e-4 keeps the gas-side kinematic
+    Laplace pressure sigma/(R rho2) and the buoyancy pressure difference across the
+    largest bubble below ~1e-3, the range in which the scheme stays stable at a
+    density ratio of 1000 (g = 5.85e-9, sigma = 2.87e-6, mu1 = 1.28e-3)."""
     rng = np.random.default_rng(seed)
     W = 4.0
     bl = place_bubbles(n, nb, rmin, rmax, W, rng)

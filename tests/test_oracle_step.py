@@ -127,10 +127,10 @@ def test_fd_correction_on_tanh_converges():
     for W in (4.0, 8.0, 16.0):
         n = int(16 * W)
         phi = _tanh_line(W, n)
-        prm = oracle.Params(nx=8, ny=n, W=W, lam=0.05, M=0.0, sigma=0.0)
+        prm = oracle.Params(nx=8, ny=n, W=W, lam=0.05, M=0.0, sigma=0.0, eps=1e-12)
         L_ = S.fd_rhs(phi, prm)
         errs.append(float(L_.abs().max()))
-    # J_phi(tanh) = 0 in the continuum; the discrete L decays at least like W^-4
+    # J_phi(tanh) = 0 in the continuum (eps -> 0); the discrete L decays at least like W^-4
     assert errs[0] < 1e-3
     assert errs[0] / errs[1] > 12 and errs[1] / errs[2] > 12
 

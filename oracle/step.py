@@ -198,14 +198,16 @@ def src_f(phi, ax, ay):
 
 def src_g(Fx, Fy, rho, ux, uy, bx, by):
     """NS source, eq:Gi with reading R8 (b = F/rho - grad p):
-    G_i = w_i [ c_i.F / (rho c_s^2) + (u b):(c_i c_i - c_s^2 I) / c_s^4 ]."""
+    G_i = w_i [ c_i.(F/rho) / c_s^2 + (u b):(c_i c_i - c_s^2 I) / c_s^4 ]."""
+    Frx = Fx / rho
+    Fry = Fy / rho
     ub = ux * bx + uy * by
     out = []
     for i in range(9):
-        cF = _cdot(i, Fx, Fy)
+        cF = _cdot(i, Frx, Fry)
         cu = _cdot(i, ux, uy)
         cb = _cdot(i, bx, by)
-        out.append(W[i] * ((cF * 3.0) / rho + ((cu * cb) - ub / 3.0) * 9.0))
+        out.append(W[i] * ((cF * 3.0) + ((cu * cb) - ub / 3.0) * 9.0))
     return out
 
 

@@ -48,6 +48,19 @@ __device__ __forceinline__ int map_idx(int i, int n, int wall, int& flip) {
   return i < 0 ? 0 : (i >= n ? n - 1 : i);
 }
 
+// Tile of this workgroup.  Workgroups are dealt round-robin to the 8 XCDs
+// (XCD = blockIdx mod 8), each with its own L2; the remap gives every XCD a
+// contiguous band of tiles (row-major), so halo reads and the neighbour
+// writes of the in-place streaming mostly stay inside one L2.  A bijection
+// of [0, gridDim.x) for any tile count.
+__device__ __forceinline__ void tile_of(int tiles_x, int& tx, int& ty) {
+  const int nb = (int)gridDim.x, b = (int)blockIdx.x;
+  const int q = nb >> 3, r = nb & 7, k = b & 7, j = b >> 3;
+  const int t = k * q + (k < r ? k : r) + j;
+  ty = t / tiles_x;
+  tx = t - ty * tiles_x;
+}
+
 // load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS
 template <typename T, typename S, int NT>
 __device__ __forceinline__ void load_window(T* dst, int RW, int RH, const S* __restrict__ src,
@@ -63,34 +76,34 @@ __device__ __forceinline__ void load_window(T* dst, int RW, int RH, const S* __r
 }
 
 // ------------------------------------------------------------- populations
-template <typename T, int PAR>
-__device__ __forceinline__ T pull(const T* __restrict__ A, const KParams<T>& P, int i, int x, int y) {
-  if (PAR == 1) return A[i * P.ps + (long long)y * P.nx + x];
-  const int cx = cx_of(i), cy = cy_of(i);
-  int sx = x - cx, sy = y - cy;
-  const bool outside = (P.wx && (sx < 0 || sx >= P.nx)) || (P.wy && (sy < 0 || sy >= P.ny));
-  if (outside) return A[i * P.ps + (long long)y * P.nx + x];
-  sx = sx < 0 ? sx + P.nx : (sx >= P.nx ? sx - P.nx : sx);
-  sy = sy < 0 ? sy + P.ny : (sy >= P.ny ? sy - P.ny : sy);
-  return A[opp(i) * P.ps + (long long)sy * P.nx + sx];
-}
-
-template <typename T, int PAR>
-__device__ __forceinline__ void push(T* __restrict__ A, const KParams<T>& P, int i, int x, int y, T v) {
+// Element offsets (from a distribution's base) of the nine slots node (x, y)
+// pulls f_i from.  In both parities the node writes f*_opp(i) back to the slot
+// it pulled f_i from (parity 0: the slot of x - c_i, or its own slot i beyond a
+// wall; parity 1: its own slot i), so one set of offsets serves the pull and
+// the push of f and of g.  32-bit offsets: 9 planes < 2^31 elements (checked
+// at context creation).
+template <int PAR, typename T>
+__device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[9]) {
+  const int ps = (int)P.ps;
+  const int id = y * P.nx + x;
   if (PAR == 1) {
-    A[opp(i) * P.ps + (long long)y * P.nx + x] = v;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) rd[i] = i * ps + id;
     return;
   }
-  const int cx = cx_of(i), cy = cy_of(i);
-  int tx = x + cx, ty = y + cy;
-  const bool outside = (P.wx && (tx < 0 || tx >= P.nx)) || (P.wy && (ty < 0 || ty >= P.ny));
-  if (outside) {
-    A[opp(i) * P.ps + (long long)y * P.nx + x] = v;
-    return;
+  const bool lo_x = x == 0, hi_x = x == P.nx - 1, lo_y = y == 0, hi_y = y == P.ny - 1;
+  const int xm = lo_x ? P.nx - 1 : x - 1, xp = hi_x ? 0 : x + 1;
+  const int rm = (lo_y ? P.ny - 1 : y - 1) * P.nx, r0 = y * P.nx, rp = (hi_y ? 0 : y + 1) * P.nx;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cx = cx_of(i), cy = cy_of(i);
+    // source node x - c_i
+    const int sx = cx == 1 ? xm : (cx == -1 ? xp : x);
+    const int sr = cy == 1 ? rm : (cy == -1 ? rp : r0);
+    const bool out = (P.wx && ((cx == 1 && lo_x) || (cx == -1 && hi_x))) ||
+                     (P.wy && ((cy == 1 && lo_y) || (cy == -1 && hi_y)));
+    rd[i] = out ? i * ps + id : opp(i) * ps + sr + sx;
   }
-  tx = tx < 0 ? tx + P.nx : (tx >= P.nx ? tx - P.nx : tx);
-  ty = ty < 0 ? ty + P.ny : (ty >= P.ny ? ty - P.ny : ty);
-  A[i * P.ps + (long long)ty * P.nx + tx] = v;
 }
 
 // ------------------------------------------------------------ a1: gather
@@ -104,14 +117,16 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  T s = pull<T, PAR>(Af, P, 0, x, y);
+  int rd[9];
+  slots<PAR>(P, x, y, rd);
+  T s = Af[rd[0]];
 #pragma unroll
-  for (int i = 1; i < 9; ++i) s = s + pull<T, PAR>(Af, P, i, x, y);
+  for (int i = 1; i < 9; ++i) s = s + Af[rd[i]];
   phibar[id] = s;
   if (!COUPLED) return;
   T g[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = pull<T, PAR>(Ag, P, i, x, y);
+  for (int i = 0; i < 9; ++i) g[i] = Ag[rd[i]];
   T sg = g[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) sg = sg + g[i];
@@ -136,7 +151,7 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
 // L(phi*) = div_4 (lambda J_phi + q)  (eq:final_mCHE, eq:fourOrder_FDM) and the
 // TVD-RK3 combination of eq:TVD-3order for STAGE 1, 2, 3.
 template <typename T, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(256) void k_fd(KParams<T> P, const T* __restrict__ in,
+__global__ __launch_bounds__(256) void k_fd(KParams<T> P, int tiles_x, const T* __restrict__ in,
                                             const T* __restrict__ phibar, T* __restrict__ out) {
   constexpr int NT = 256;
   constexpr int W5 = TX + 10, H5 = TY + 10;   // phi*, halo 5
@@ -146,7 +161,9 @@ __global__ __launch_bounds__(256) void k_fd(KParams<T> P, const T* __restrict__ 
   __shared__ T sM[W4 * H4];
   __shared__ T sJx[W2 * H2];
   __shared__ T sJy[W2 * H2];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
   load_window<T, T, NT>(sP, W5, H5, in, x0 - 5, y0 - 5, P, false);
   __syncthreads();
   const Tile<T> tP{sP, W5, 5}, tM{sM, W4, 4}, tJx{sJx, W2, 2}, tJy{sJy, W2, 2};
@@ -261,73 +278,142 @@ __device__ __forceinline__ void node_force(const Tile<T>& tP, const Tile<T>& tPx
   Fy = (((Fpy + Fsy) + Fny) + Fmy) + Fgy;
 }
 
-// ------------------------------------------- a3: velocity fixed-point sweep
-// u^{k+1} = j + F(u^k) / (2 rho)   (Eq:u)
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(256) void k_vel(KParams<T> P, const T* __restrict__ phi,
+// ------------------------------------------- a3: velocity fixed-point sweeps
+// u^{k+1} = j + F(u^k) / (2 rho)   (Eq:u), KS consecutive sweeps in one launch:
+// sweep k is evaluated on the tile grown by KS-1-k nodes, so the next sweep
+// finds its halo in LDS.  Every sweep computes exactly what a one-sweep launch
+// computes at the same node.
+template <typename T, int KS, int TX, int TY>
+__global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                              const T* __restrict__ praw, const T* __restrict__ jx,
                                              const T* __restrict__ jy, const T* __restrict__ uxi,
                                              const T* __restrict__ uyi, T* __restrict__ uxo,
                                              T* __restrict__ uyo) {
   constexpr int NT = 256;
-  constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
-  __shared__ T sP[W2 * H2];
-  __shared__ T sPx[W1 * H1], sPy[W1 * H1], sMu[W1 * H1], sRho[W1 * H1], sUx[W1 * H1],
-      sUy[W1 * H1];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
-  load_window<T, T, NT>(sUx, W1, H1, uxi, x0 - 1, y0 - 1, P, true);
-  load_window<T, T, NT>(sUy, W1, H1, uyi, x0 - 1, y0 - 1, P, true);
+  constexpr int HP = KS + 1;                      // phi halo
+  constexpr int WP = TX + 2 * HP, HPH = TY + 2 * HP;
+  constexpr int WD = TX + 2 * KS, HD = TY + 2 * KS;  // derived fields and u^0
+  __shared__ T sP[WP * HPH];
+  __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
+  __shared__ T sU[2][2][WD * HD];                 // ping-pong velocity iterates
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT>(sP, WP, HPH, phi, x0 - HP, y0 - HP, P, false);
+  load_window<T, T, NT>(sU[0][0], WD, HD, uxi, x0 - KS, y0 - KS, P, true);
+  load_window<T, T, NT>(sU[0][1], WD, HD, uyi, x0 - KS, y0 - KS, P, true);
   __syncthreads();
-  const Tile<T> tP{sP, W2, 2};
-  derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
+  const Tile<T> tP{sP, WP, HP};
+  for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
+    const int ly = idx / WD - KS, lx = idx % WD - KS;
+    T gx, gy;
+    iso_grad<T>(tP, lx, ly, gx, gy);
+    sPx[idx] = gx;
+    sPy[idx] = gy;
+    sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
+    sRho[idx] = density<T>(tP(lx, ly), P.rho1, P.rho2);
+  }
   __syncthreads();
-  const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
-      tUx{sUx, W1, 1}, tUy{sUy, W1, 1};
-  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
-    const int ly = idx / TX, lx = idx % TX;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= P.nx || y >= P.ny) continue;
-    const long long id = (long long)y * P.nx + x;
-    T Fx, Fy, rho, nu, a, b, c, d;
-    node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, praw[id], lx, ly, P, Fx, Fy, rho, nu, a, b,
-                  c, d);
-    uxo[id] = jx[id] + Fx / (T(2) * rho);
-    uyo[id] = jy[id] + Fy / (T(2) * rho);
+  const Tile<T> tPx{sPx, WD, KS}, tPy{sPy, WD, KS}, tMu{sMu, WD, KS}, tRho{sRho, WD, KS};
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    const int g = KS - 1 - k;                     // output halo of this sweep
+    const int RW = TX + 2 * g, RH = TY + 2 * g;
+    const Tile<T> tUx{sU[k & 1][0], WD, KS}, tUy{sU[k & 1][1], WD, KS};
+    T* ox = sU[(k + 1) & 1][0];
+    T* oy = sU[(k + 1) & 1][1];
+    for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
+      const int ly = idx / RW - g, lx = idx % RW - g;
+      const int gxn = x0 + lx, gyn = y0 + ly;
+      // ghosts beyond a wall are filled below from their mirror node
+      if ((P.wx && (gxn < 0 || gxn >= P.nx)) || (P.wy && (gyn < 0 || gyn >= P.ny))) continue;
+      if (g == 0 && (gxn >= P.nx || gyn >= P.ny)) continue;
+      int flip = 0;
+      const int x = map_idx(gxn, P.nx, P.wx, flip);
+      const int y = map_idx(gyn, P.ny, P.wy, flip);
+      const long long id = (long long)y * P.nx + x;
+      T Fx, Fy, rho, nu, a, b, c, d;
+      node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, praw[id], lx, ly, P, Fx, Fy, rho, nu, a, b,
+                    c, d);
+      const T vx = jx[id] + Fx / (T(2) * rho);
+      const T vy = jy[id] + Fy / (T(2) * rho);
+      if (g == 0) {
+        uxo[id] = vx;
+        uyo[id] = vy;
+      } else {
+        const int o = (ly + KS) * WD + (lx + KS);
+        ox[o] = vx;
+        oy[o] = vy;
+      }
+    }
+    __syncthreads();
+    if (g > 0 && (P.wx || P.wy)) {
+      // no-slip ghosts: the mirror node's value with its sign flipped once per
+      // mirrored axis (as the oracle's ghost extension does)
+      for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
+        const int ly = idx / RW - g, lx = idx % RW - g;
+        const int gxn = x0 + lx, gyn = y0 + ly;
+        int mx = gxn, my = gyn, flips = 0;
+        if (P.wx && gxn < 0) { mx = -1 - gxn; flips ^= 1; }
+        if (P.wx && gxn >= P.nx) { mx = 2 * P.nx - 1 - gxn; flips ^= 1; }
+        if (P.wy && gyn < 0) { my = -1 - gyn; flips ^= 1; }
+        if (P.wy && gyn >= P.ny) { my = 2 * P.ny - 1 - gyn; flips ^= 1; }
+        if (mx == gxn && my == gyn) continue;            // not a ghost
+        const int lmx = mx - x0, lmy = my - y0;
+        const int o = (ly + KS) * WD + (lx + KS);
+        if (lmx < -g || lmx >= TX + g || lmy < -g || lmy >= TY + g) {
+          ox[o] = T(0);                                  // never read by an in-domain output
+          oy[o] = T(0);
+          continue;
+        }
+        const int om = (lmy + KS) * WD + (lmx + KS);
+        ox[o] = flips ? -ox[om] : ox[om];
+        oy[o] = flips ? -oy[om] : oy[om];
+      }
+      __syncthreads();
+    }
   }
 }
 
 // ------------------------------------------------ a4: explicit selective filter
 // chi <- chi - a [ sum_j d_|j| chi(x+j, y) + sum_j d_|j| chi(x, y+j) ]  (eq:filter)
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(256) void k_filter(KParams<T> P, const T* __restrict__ pin,
+template <typename T, int N, int TX, int TY>
+__global__ __launch_bounds__(256) void k_filter(KParams<T> P, int tiles_x, const T* __restrict__ pin,
                                                 const T* __restrict__ uxin,
                                                 const T* __restrict__ uyin, T* __restrict__ pout,
                                                 T* __restrict__ uxout, T* __restrict__ uyout) {
   constexpr int NT = 256;
-  constexpr int W5 = TX + 10, H5 = TY + 10;
-  __shared__ T s0[W5 * H5], s1[W5 * H5], s2[W5 * H5];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-  load_window<T, T, NT>(s0, W5, H5, pin, x0 - 5, y0 - 5, P, false);
-  load_window<T, T, NT>(s1, W5, H5, uxin, x0 - 5, y0 - 5, P, true);
-  load_window<T, T, NT>(s2, W5, H5, uyin, x0 - 5, y0 - 5, P, true);
+  constexpr int WN = TX + 2 * N, HN = TY + 2 * N;
+  __shared__ T s0[WN * HN], s1[WN * HN], s2[WN * HN];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT>(s0, WN, HN, pin, x0 - N, y0 - N, P, false);
+  load_window<T, T, NT>(s1, WN, HN, uxin, x0 - N, y0 - N, P, true);
+  load_window<T, T, NT>(s2, WN, HN, uyin, x0 - N, y0 - N, P, true);
   __syncthreads();
-  const int N = P.fn;
+  T d[N + 1];
+#pragma unroll
+  for (int j = 0; j <= N; ++j) d[j] = P.fd[j];
+  const T a = P.fa;
   for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
     const int ly = idx / TX, lx = idx % TX;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) continue;
     const long long id = (long long)y * P.nx + x;
-    const T* src[3] = {s0, s1, s2};
-    T* dst[3] = {pout, uxout, uyout};
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-      const Tile<T> t{const_cast<T*>(src[f]), W5, 5};
-      T sx = P.fd[N] * t(lx - N, ly);
-      for (int j = -N + 1; j <= N; ++j) sx = sx + P.fd[j < 0 ? -j : j] * t(lx + j, ly);
-      T sy = P.fd[N] * t(lx, ly - N);
-      for (int j = -N + 1; j <= N; ++j) sy = sy + P.fd[j < 0 ? -j : j] * t(lx, ly + j);
-      dst[f][id] = t(lx, ly) - P.fa * (sx + sy);
+      const Tile<T> t{f == 0 ? s0 : f == 1 ? s1 : s2, WN, N};
+      T sx = d[N] * t(lx - N, ly);
+#pragma unroll
+      for (int j = -N + 1; j <= N; ++j) sx = sx + d[j < 0 ? -j : j] * t(lx + j, ly);
+      T sy = d[N] * t(lx, ly - N);
+#pragma unroll
+      for (int j = -N + 1; j <= N; ++j) sy = sy + d[j < 0 ? -j : j] * t(lx, ly + j);
+      const T r = t(lx, ly) - a * (sx + sy);
+      if (f == 0) pout[id] = r;
+      else if (f == 1) uxout[id] = r;
+      else uyout[id] = r;
     }
   }
 }
@@ -336,7 +422,7 @@ __global__ __launch_bounds__(256) void k_filter(KParams<T> P, const T* __restric
 // MRT collision of f (eq:distribution_CH) and g (eq:distribution_NS) at n+1,
 // written to the streaming slots of the other parity.
 template <typename T, int PAR, bool COUPLED, int TX, int TY>
-__global__ __launch_bounds__(256) void k_collide(KParams<T> P, T* __restrict__ Af, T* __restrict__ Ag,
+__global__ __launch_bounds__(256) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
                                                  const T* __restrict__ phi, const T* __restrict__ pt,
                                                  const T* __restrict__ ux, const T* __restrict__ uy,
                                                  const T* __restrict__ uox,
@@ -346,7 +432,9 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, T* __restrict__ A
   __shared__ T sP[W2 * H2];
   __shared__ T sPx[COUPLED ? W1 * H1 : 1], sPy[COUPLED ? W1 * H1 : 1], sMu[W1 * H1],
       sRho[COUPLED ? W1 * H1 : 1], sUx[W1 * H1], sUy[W1 * H1], sPt[COUPLED ? W1 * H1 : 1];
-  const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
   load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
   load_window<T, T, NT>(sUx, W1, H1, ux, x0 - 1, y0 - 1, P, true);
   load_window<T, T, NT>(sUy, W1, H1, uy, x0 - 1, y0 - 1, P, true);
@@ -376,15 +464,17 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, T* __restrict__ A
     iso_grad<T>(tUy, lx, ly, duyx, duyy);
     const T ax = (u_x - uox[id]) + (u_x * duxx + u_y * duxy);
     const T ay = (u_y - uoy[id]) + (u_x * duyx + u_y * duyy);
+    int rd[9];
+    slots<PAR>(P, x, y, rd);
     {
       T f[9], feq[9], F[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = pull<T, PAR>(Af, P, i, x, y);
+      for (int i = 0; i < 9; ++i) f[i] = Af[rd[i]];
       f_eq<T>(ph, tMu(lx, ly), u_x, u_y, P.eta, feq);
       src_f<T>(ph, ax, ay, F);
       mrt_collide<T>(f, feq, F, P.s_f);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) push<T, PAR>(Af, P, i, x, y, f[i]);
+      for (int i = 0; i < 9; ++i) Af[rd[opp(i)]] = f[i];
     }
     if (COUPLED) {
       const T p = tPt(lx, ly);
@@ -392,12 +482,13 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, T* __restrict__ A
       node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, lx, ly, P, Fx, Fy, rho, nu, a, b, c, d);
       T dpx, dpy;
       iso_grad<T>(tPt, lx, ly, dpx, dpy);
-      const T bx = Fx / rho - dpx, by = Fy / rho - dpy;
+      const T Frx = Fx / rho, Fry = Fy / rho;
+      const T bx = Frx - dpx, by = Fry - dpy;
       T g[9], geq[9], G[9], s[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) g[i] = pull<T, PAR>(Ag, P, i, x, y);
+      for (int i = 0; i < 9; ++i) g[i] = Ag[rd[i]];
       g_eq<T>(p, u_x, u_y, geq);
-      src_g<T>(Fx, Fy, rho, u_x, u_y, bx, by, G);
+      src_g<T>(Frx, Fry, u_x, u_y, bx, by, G);
       const T tau_g = nu * T(3) + T(0.5);
       const T sv = T(1) / tau_g;
 #pragma unroll
@@ -406,7 +497,7 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, T* __restrict__ A
       s[8] = sv;
       mrt_collide<T>(g, geq, G, s);
 #pragma unroll
-      for (int i = 0; i < 9; ++i) push<T, PAR>(Ag, P, i, x, y, g[i]);
+      for (int i = 0; i < 9; ++i) Ag[rd[opp(i)]] = g[i];
     }
   }
 }

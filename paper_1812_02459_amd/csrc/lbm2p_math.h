@@ -146,17 +146,17 @@ __device__ __forceinline__ void src_f(T phi, T ax, T ay, T F[9]) {
   for (int i = 1; i < 9; ++i) F[i] = ((T(w_of(i)) * phi) * cdot(i, ax, ay)) * T(3);
 }
 
-// eq:Gi with b = F/rho - grad p:
-//   G_i = w_i [ c_i.F / (rho c_s^2) + ((c_i.u)(c_i.b) - c_s^2 u.b) / c_s^4 ]
+// eq:Gi with b = F/rho - grad p, given (Frx, Fry) = F/rho:
+//   G_i = w_i [ c_i.(F/rho) / c_s^2 + ((c_i.u)(c_i.b) - c_s^2 u.b) / c_s^4 ]
 template <typename T>
-__device__ __forceinline__ void src_g(T Fx, T Fy, T rho, T ux, T uy, T bx, T by, T G[9]) {
+__device__ __forceinline__ void src_g(T Frx, T Fry, T ux, T uy, T bx, T by, T G[9]) {
   const T ub = ux * bx + uy * by;
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const T cF = cdot(i, Fx, Fy);
+    const T cF = cdot(i, Frx, Fry);
     const T cu = cdot(i, ux, uy);
     const T cb = cdot(i, bx, by);
-    G[i] = T(w_of(i)) * ((cF * T(3)) / rho + ((cu * cb) - ub / T(3)) * T(9));
+    G[i] = T(w_of(i)) * ((cF * T(3)) + ((cu * cb) - ub / T(3)) * T(9));
   }
 }
 

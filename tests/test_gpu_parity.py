@@ -100,7 +100,9 @@ def test_ch_only_vortex_config_size_1000_steps():
 
 def test_original_ch_and_filter_variants():
     for kw in (dict(original_ch=True), dict(filter_n=5), dict(filter_n=0), dict(K=3),
-               dict(filter_n=9, filter_a=0.3)):
+               dict(filter_n=9, filter_a=0.3), dict(filter_n=7), dict(K=1),
+               dict(K=3, wall_y=True), dict(K=4, wall_x=True, wall_y=True),
+               dict(eps=1e-9)):
         wl = droplet_case(48, 40, seed=3, **kw)
         st, prm = oracle_init(wl)
         sim = gpu_sim(wl)

@@ -30,6 +30,34 @@ def step_values(K):
     return 22 + 8 + 8 * K + 6 + 42
 
 
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_collide_bubbles4096_hbm_traffic.md")
+KERNEL_SOURCES = ["lbm2p_kernels.h", "lbm2p_math.h", "lbm2p_impl.h", "lbm2p_f32.hip"]
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1812_02459_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per collide launch from the committed rocprofv3 counter summary,
+    or None when the kernel sources changed after the counters were taken."""
+    try:
+        for line in open(TRAFFIC_FILE):
+            if line.startswith("traffic_json: "):
+                d = json.loads(line[len("traffic_json: "):])
+                if d.get("source_sha256") == kernel_source_hash():
+                    return d["bytes_per_launch"]
+    except OSError:
+        pass
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +182,7 @@ def main():
         print(f"# cpu oracle: {cpu['value']:.3f} MLUPS on {cpu['cores']} threads",
               file=sys.stderr, flush=True)
     nodes = args.n * args.n
+    traffic = measured_traffic() if args.n == 4096 else None
     out = {
         "metric": "coupled-step MLUPS + %HBM roofline, FP32 vs FP64 at stated error; "
                   "adjoint/forward time",
@@ -182,7 +211,9 @@ def main():
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(r32["collide_gbps"] / HBM_PEAK_GBPS, 4),
-            "traffic": None,
+            "traffic": (round(traffic / (r32["collide_ms"] * 1e-3) / 1e9, 1)
+                        if traffic else None),
+            "traffic_bytes_per_launch": traffic,
             "bytes_per_launch": r32["collide_bytes"],
             "avg_launch_ms": round(r32["collide_ms"], 4),
         },

@@ -295,7 +295,8 @@ __global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T*
   constexpr int WD = TX + 2 * KS, HD = TY + 2 * KS;  // derived fields and u^0
   __shared__ T sP[WP * HPH];
   __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
-  __shared__ T sU[2][2][WD * HD];                 // ping-pong velocity iterates
+  constexpr int NB = KS > 1 ? 2 : 1;               // the last sweep writes to HBM
+  __shared__ T sU[NB][2][WD * HD];                // ping-pong velocity iterates
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
@@ -319,9 +320,9 @@ __global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T*
   for (int k = 0; k < KS; ++k) {
     const int g = KS - 1 - k;                     // output halo of this sweep
     const int RW = TX + 2 * g, RH = TY + 2 * g;
-    const Tile<T> tUx{sU[k & 1][0], WD, KS}, tUy{sU[k & 1][1], WD, KS};
-    T* ox = sU[(k + 1) & 1][0];
-    T* oy = sU[(k + 1) & 1][1];
+    const Tile<T> tUx{sU[(k & 1) % NB][0], WD, KS}, tUy{sU[(k & 1) % NB][1], WD, KS};
+    T* ox = sU[((k + 1) & 1) % NB][0];
+    T* oy = sU[((k + 1) & 1) % NB][1];
     for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
       const int ly = idx / RW - g, lx = idx % RW - g;
       const int gxn = x0 + lx, gyn = y0 + ly;

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstdint>
 #include <new>
 #include <vector>
@@ -35,7 +36,9 @@ int validate(const lbm2p_params* p) {
   if (p->filter_n != 0 && p->filter_n != 5 && p->filter_n != 7 && p->filter_n != 9 &&
       p->filter_n != 11)
     return LBM2P_EINVAL;
-  if (p->compact) return LBM2P_EINVAL;  // compact variant: not in this library build
+  if (p->compact != 0 && p->compact != 1) return LBM2P_EINVAL;
+  if (p->compact && (p->compact_n < 1 || p->compact_n > 5)) return LBM2P_EINVAL;
+  if (p->compact && !(p->compact_alpha > -0.5 && p->compact_alpha < 0.5)) return LBM2P_EINVAL;
   if (p->K < 1 || p->K > 8) return LBM2P_EINVAL;
   if (!(p->filter_a >= 0 && p->filter_a <= 1)) return LBM2P_EINVAL;
   if (p->coupled != 0 && p->coupled != 1) return LBM2P_EINVAL;
@@ -52,10 +55,87 @@ size_t n_planes(const lbm2p_params* p) {
   return p->coupled ? 9 + 4 + 4 + 9 + 4 + 4 : 9 + 4 + 4;
 }
 
+size_t compact_planes(const lbm2p_params* p) { return (p->coupled && p->compact) ? 9 : 0; }
+
+size_t compact_table_doubles(const lbm2p_params* p) {
+  if (!(p->coupled && p->compact)) return 0;
+  return 2 * 3 * ((size_t)p->nx + (size_t)p->ny);  // 2 parities x (cp, inv, z) per axis
+}
+
 size_t ws_size(const lbm2p_params* p) {
   const size_t esz = p->precision ? 4 : 8;
-  return n_planes(p) * (size_t)plane_stride(p) * esz + (RED_BLOCKS + 1) * RED_K * sizeof(double) +
-         256;
+  return (n_planes(p) + compact_planes(p)) * (size_t)plane_stride(p) * esz +
+         (RED_BLOCKS + 1) * RED_K * sizeof(double) + compact_table_doubles(p) * sizeof(double) +
+         512;
+}
+
+// Coefficients a_0..a_N of the compact filter: T(0) = 1, T(pi) = 0 and the
+// vanishing w^2 .. w^(2N-2) Taylor terms of T(w) - 1, with
+// T(w) = sum a_n cos(n w) / (1 + 2 alpha cos w).  Gaussian elimination with
+// partial pivoting on the (N+1) x (N+1) system.
+void compact_coeffs(int N, double alpha, double* a) {
+  double A[6][7];
+  for (int n = 0; n <= N; ++n) A[0][n] = 1.0;
+  A[0][N + 1] = 1.0 + 2.0 * alpha;
+  for (int k = 1; k < N; ++k) {
+    for (int n = 0; n <= N; ++n) A[k][n] = std::pow((double)n, 2.0 * k);
+    A[k][N + 1] = 2.0 * alpha;
+  }
+  for (int n = 0; n <= N; ++n) A[N][n] = (n % 2) ? -1.0 : 1.0;
+  A[N][N + 1] = 0.0;
+  const int m = N + 1;
+  for (int c = 0; c < m; ++c) {
+    int piv = c;
+    for (int r = c + 1; r < m; ++r)
+      if (std::fabs(A[r][c]) > std::fabs(A[piv][c])) piv = r;
+    for (int k = 0; k <= m; ++k) std::swap(A[c][k], A[piv][k]);
+    for (int r = 0; r < m; ++r) {
+      if (r == c) continue;
+      const double f = A[r][c] / A[c][c];
+      for (int k = c; k <= m; ++k) A[r][k] -= f * A[c][k];
+    }
+  }
+  for (int n = 0; n < 6; ++n) a[n] = n < m ? A[n][m] / A[n][n] : 0.0;
+}
+
+// Thomas tables of the line matrix (1 on the diagonal, alpha off it) for n
+// nodes: periodic -> cyclic matrix split as B + u v^T (Sherman-Morrison with
+// gamma = -1); wall -> end rows 1 + sgn alpha (mirror ghosts).
+void compact_table(int n, double alpha, bool cyclic, double sgn, double* cp, double* inv,
+                   double* z, double* fac, double* den) {
+  std::vector<double> b(n, 1.0);
+  double gamma = 0;
+  if (cyclic) {
+    gamma = -1.0;
+    b[0] = 1.0 - gamma;
+    b[n - 1] = 1.0 - alpha * alpha / gamma;
+  } else {
+    b[0] = 1.0 + sgn * alpha;
+    b[n - 1] = 1.0 + sgn * alpha;
+  }
+  double c_prev = 0;
+  for (int i = 0; i < n; ++i) {
+    const double piv = b[i] - (i ? alpha * c_prev : 0.0);
+    inv[i] = 1.0 / piv;
+    cp[i] = alpha * inv[i];
+    c_prev = cp[i];
+  }
+  if (cyclic) {
+    // B z = u with u = (gamma, 0, ..., 0, alpha)
+    std::vector<double> d(n);
+    for (int i = 0; i < n; ++i) {
+      const double r = i == 0 ? gamma : (i == n - 1 ? alpha : 0.0);
+      d[i] = (i ? r - alpha * d[i - 1] : r) * inv[i];
+    }
+    z[n - 1] = d[n - 1];
+    for (int i = n - 2; i >= 0; --i) z[i] = d[i] - cp[i] * z[i + 1];
+    *fac = alpha / gamma;
+    *den = 1.0 + z[0] + (*fac) * z[n - 1];
+  } else {
+    for (int i = 0; i < n; ++i) z[i] = 0.0;
+    *fac = 0;
+    *den = 1;
+  }
 }
 
 // filter coefficients d_0..d_N of App. B
@@ -138,7 +218,28 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   } else {
     c->Ag = c->praw = c->jx = c->jy = c->pt = nullptr;
   }
+  c->cscratch = compact_planes(p) ? take((long long)compact_planes(p)) : nullptr;
   c->red = (double*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
+  c->ctab_dev = nullptr;
+  c->ctab_uploaded = 0;
+  if (compact_table_doubles(p)) {
+    c->ctab_dev = c->red + (RED_BLOCKS + 1) * RED_K;
+    c->ctab_host.assign(compact_table_doubles(p), 0.0);
+    compact_coeffs(p->compact_n, p->compact_alpha, c->ca);
+    size_t off = 0;
+    for (int axis = 0; axis < 2; ++axis) {
+      const int n = axis == 0 ? p->nx : p->ny;
+      const bool cyclic = axis == 0 ? !p->wall_x : !p->wall_y;
+      c->ctab_n[axis] = n;
+      for (int par = 0; par < 2; ++par) {
+        c->ctab_off[axis][par] = off;
+        double* base = c->ctab_host.data() + off;
+        compact_table(n, p->compact_alpha, cyclic, par ? -1.0 : 1.0, base, base + n, base + 2 * n,
+                      &c->cfac[axis][par], &c->cden[axis][par]);
+        off += 3 * (size_t)n;
+      }
+    }
+  }
   // derived constants, written as the oracle writes them (Sec. 2.1, eq:mobility)
   c->kappa = 3.0 * p->sigma * p->W / 8.0;
   c->beta = 3.0 * p->sigma / (4.0 * p->W);

@@ -30,6 +30,16 @@ struct lbm2p_ctx {
   double s_f[9], s_g[9];
   double fd[6];
   int fn;
+  // compact filter: scratch planes (d, Fx, Fy; 3 fields each), line tables in
+  // the workspace (device) and their host image, coefficients a_n
+  void* cscratch;
+  double* ctab_dev;
+  std::vector<double> ctab_host;
+  double ca[6];
+  double cfac[2][2], cden[2][2];
+  size_t ctab_off[2][2];  // offsets (in doubles) of each (axis, parity) table
+  int ctab_n[2];
+  int ctab_uploaded;
   // profiling
   int prof_pass;
   std::vector<hipEvent_t> ev0, ev1;

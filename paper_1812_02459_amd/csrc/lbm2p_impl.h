@@ -8,6 +8,7 @@
 
 #include "lbm2p_ctx.h"
 #include "lbm2p_kernels.h"
+#include "lbm2p_compact.h"
 
 namespace lbm2p {
 namespace {
@@ -268,6 +269,34 @@ struct ProfScope {
 };
 
 template <typename T>
+CompactArgs<T> compact_args(const lbm2p_ctx* c) {
+  CompactArgs<T> A;
+  for (int k = 0; k < 6; ++k) A.a[k] = c->ca[k];
+  A.alpha = c->p.compact_alpha;
+  for (int axis = 0; axis < 2; ++axis)
+    for (int par = 0; par < 2; ++par) {
+      const int n = c->ctab_n[axis];
+      const double* base = c->ctab_dev + c->ctab_off[axis][par];
+      A.line[axis][par] = CompactLine{base, base + n, base + 2 * n, c->cfac[axis][par],
+                                      c->cden[axis][par],
+                                      axis == 0 ? !c->p.wall_x : !c->p.wall_y};
+    }
+  return A;
+}
+
+template <typename T, int N>
+void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, const T* uy,
+                    T* po, T* uxo, T* uyo) {
+  const CompactArgs<T> A = compact_args<T>(c);
+  T* d = (T*)c->cscratch;
+  T* fx = d + 3 * c->ps;
+  T* fy = d + 6 * c->ps;
+  k_compact_x<T, N><<<(3 * c->p.ny + 63) / 64, 64, 0, c->stream>>>(K, A, p, ux, uy, d, fx);
+  k_compact_y<T, N><<<(3 * c->p.nx + 63) / 64, 64, 0, c->stream>>>(K, A, p, ux, uy, d, fx, fy,
+                                                                   po, uxo, uyo);
+}
+
+template <typename T>
 int step_impl(lbm2p_ctx* c, int nsteps) {
   const lbm2p_params& p = c->p;
   const KParams<T> K = kparams<T>(c);
@@ -346,7 +375,17 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         ++launch;
       }
       c->uk_last = (launch - 1) & 1;
-      if (p.filter_n == 0) {
+      if (p.compact) {
+        ProfScope ps(c, PASS_FILTER);
+        const T* pr = (const T*)c->praw;
+        switch (p.compact_n) {
+          case 1: launch_compact<T, 1>(c, K, pr, ux, uy, (T*)c->pt, unx, uny); break;
+          case 2: launch_compact<T, 2>(c, K, pr, ux, uy, (T*)c->pt, unx, uny); break;
+          case 3: launch_compact<T, 3>(c, K, pr, ux, uy, (T*)c->pt, unx, uny); break;
+          case 4: launch_compact<T, 4>(c, K, pr, ux, uy, (T*)c->pt, unx, uny); break;
+          default: launch_compact<T, 5>(c, K, pr, ux, uy, (T*)c->pt, unx, uny); break;
+        }
+      } else if (p.filter_n == 0) {
         k_copy<T><<<blocks1d(n), 256, 0, st>>>((T*)c->praw, (T*)c->pt, n);
         k_copy<T><<<blocks1d(n), 256, 0, st>>>(ux, unx, n);
         k_copy<T><<<blocks1d(n), 256, 0, st>>>(uy, uny, n);
@@ -394,6 +433,13 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
 template <typename T>
 int init_impl(lbm2p_ctx* c, const double* phi0, const double* ux0, const double* uy0,
               const double* p0) {
+  if (c->ctab_dev && !c->ctab_uploaded) {
+    if (hipMemcpyAsync(c->ctab_dev, c->ctab_host.data(), c->ctab_host.size() * sizeof(double),
+                       hipMemcpyHostToDevice, c->stream) != hipSuccess)
+      return LBM2P_EHIP;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
+    c->ctab_uploaded = 1;
+  }
   const KParams<T> K = kparams<T>(c);
   T* ux = (T*)c->U[0][0];
   T* uy = (T*)c->U[0][1];

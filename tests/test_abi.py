@@ -35,11 +35,14 @@ def test_workspace_and_validation():
     n64 = B.lbm2p_workspace_bytes(B.make_params(ok, 0))
     n32 = B.lbm2p_workspace_bytes(B.make_params(ok, 1))
     assert n64 > 34 * 64 * 48 * 8 and n32 < n64
+    nc = B.lbm2p_workspace_bytes(B.make_params(dict(ok, compact=True), 0))
+    assert nc > n64                                        # line scratch and tables
     ch = dict(ok, coupled=False)
     assert B.lbm2p_workspace_bytes(B.make_params(ch, 0)) < n64
     bad = [dict(ok, nx=15), dict(ok, rho2=0.0), dict(ok, tau_f=0.5), dict(ok, filter_n=6),
            dict(ok, K=0), dict(ok, K=9), dict(ok, filter_a=1.5), dict(ok, W=0.0),
-           dict(ok, eps=-1.0), dict(ok, mu1=-1.0)]
+           dict(ok, eps=-1.0), dict(ok, mu1=-1.0), dict(ok, compact=True, compact_n=6),
+           dict(ok, compact=True, compact_alpha=0.5), dict(ok, compact=True, compact_n=0)]
     for b in bad:
         with pytest.raises(B.LBMError, match="invalid argument"):
             B.lbm2p_workspace_bytes(B.make_params(b, 0))

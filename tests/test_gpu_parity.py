@@ -111,6 +111,26 @@ def test_original_ch_and_filter_variants():
         _compare_state(sim, st, label=str(kw))
 
 
+@pytest.mark.parametrize("kw", [
+    dict(compact=True, compact_n=5, compact_alpha=0.45),
+    dict(compact=True, compact_n=2, compact_alpha=0.3, wall_y=True),
+    dict(compact=True, compact_n=3, compact_alpha=0.49, wall_x=True, wall_y=True),
+    dict(compact=True, compact_n=1, compact_alpha=0.0, filter_a=0.8),
+])
+def test_compact_filter_variant(kw):
+    """Tridiagonal line solves on the GPU vs FFT / dense solves in the oracle
+    (not bitwise: different algorithms; the bar is still 1e-12)."""
+    wl = droplet_case(56, 48, seed=8, **kw)
+    st, prm = oracle_init(wl)
+    sim = gpu_sim(wl)
+    done = 0
+    for n in (1, 4):
+        st = oracle.run(st, prm, n - done)
+        sim.step(n - done)
+        done = n
+        _compare_state(sim, st, label=f"{kw} step {n}")
+
+
 def test_minimum_size_and_zero_steps():
     wl = droplet_case(16, 16, seed=4, R=5.0, wall_y=True)
     st, prm = oracle_init(wl)

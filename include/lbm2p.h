@@ -149,6 +149,55 @@ int lbm2p_set_state(lbm2p_ctx* c, const double* d_f, const double* d_g,
 int lbm2p_profile(lbm2p_ctx* c, int32_t pass);
 int lbm2p_profile_read(lbm2p_ctx* c, double* ms, int64_t* launches);
 
+/* ---------------------------------------------------------------- adjoint
+ * Reverse mode of n steps (discrete adjoint of the whole step above, for
+ * gradients of a loss of the final phi and state with respect to sigma, M and
+ * the initial phi0).  Each step is reversed pass by pass (collision, filter,
+ * velocity sweeps, the three FD stages, gather and streaming) with the
+ * Jacobians at the forward values, recomputed segment by segment from
+ * checkpoints kept every ckpt_every steps (memory O(n/k + k) planes, one extra
+ * forward step per step).  Supported for the explicit filter (or none), both
+ * modes, both precisions (the arithmetic of the adjoint is the context's).
+ *
+ * lbm2p_adjoint_workspace_bytes: device bytes lbm2p_record needs for these
+ * parameters, n >= 0 steps and a checkpoint interval ckpt_every >= 1.
+ * EINVAL for the compact filter (no adjoint) or invalid values. */
+int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t ckpt_every,
+                                  size_t* bytes);
+
+/* Advance n steps like lbm2p_step and keep the checkpoints of the run in
+ * d_ws (device memory, 256-byte aligned, >= the bytes above, owned by the
+ * caller and kept alive until lbm2p_adjoint returns or the next record).
+ * ESTATE before init; EINVAL for the compact filter; ENOSPACE for a small d_ws. */
+int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes);
+
+/* Inputs (seeds) and outputs of lbm2p_adjoint.  Device float64 arrays in the
+ * canonical order of lbm2p_get_state; every pointer may be NULL (a NULL seed
+ * is zero, a NULL output is not computed). */
+typedef struct lbm2p_adjoint_io {
+  const double* dL_dphi;   /* seed: dL/dphi of the last recorded step, [ny][nx]     */
+  const double* dL_df;     /* seed: dL/df* of the final state, [9][ny][nx]           */
+  const double* dL_dg;     /* seed: dL/dg* (coupled), [9][ny][nx]                    */
+  const double* dL_du;     /* seed: dL/du~ (coupled), [2][ny][nx]                    */
+  const double* phi0;      /* phi0, ux0, uy0 given to lbm2p_init_fields: needed for  */
+  const double* ux0;       /*   dL_dphi0 (ux0, uy0 may be NULL = zeros)              */
+  const double* uy0;
+  double* dL_dphi0;        /* out: dL/dphi0 [ny][nx]; the recorded run must start at */
+                           /*   lbm2p_init_fields (ESTATE otherwise)                 */
+  double* dL_df0;          /* out: dL/df* of the state the run started from          */
+  double* dL_dg0;          /* out: dL/dg* (coupled)                                  */
+  double* dL_du0;          /* out: dL/du~ (coupled)                                  */
+  double dL_dsigma;        /* out (host): total derivative with respect to sigma     */
+  double dL_dM;            /* out (host): total derivative with respect to M         */
+} lbm2p_adjoint_io;
+
+/* Run the adjoint of the last lbm2p_record: seeds at the final step, outputs at
+ * the first.  Synchronises the stream (the two scalars are host values).  The
+ * context ends in the recorded final state (phi, u~, p~ and the populations;
+ * lbm2p_fields reports an earlier step until the next lbm2p_step).  ESTATE
+ * without a matching record (or after a step, init or set_state since). */
+int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io);
+
 /* Release the context (not the workspace or the stream). */
 void lbm2p_destroy(lbm2p_ctx* c);
 

@@ -43,6 +43,16 @@ class Params(ctypes.Structure):
     ]
 
 
+class AdjointIO(ctypes.Structure):
+    _fields_ = [
+        ("dL_dphi", ctypes.c_void_p), ("dL_df", ctypes.c_void_p), ("dL_dg", ctypes.c_void_p),
+        ("dL_du", ctypes.c_void_p), ("phi0", ctypes.c_void_p), ("ux0", ctypes.c_void_p),
+        ("uy0", ctypes.c_void_p), ("dL_dphi0", ctypes.c_void_p), ("dL_df0", ctypes.c_void_p),
+        ("dL_dg0", ctypes.c_void_p), ("dL_du0", ctypes.c_void_p),
+        ("dL_dsigma", ctypes.c_double), ("dL_dM", ctypes.c_double),
+    ]
+
+
 class LBMError(RuntimeError):
     pass
 
@@ -60,6 +70,10 @@ _sig = {
     "lbm2p_set_state": [_vp, _vp, _vp, _vp],
     "lbm2p_profile": [_vp, ctypes.c_int32],
     "lbm2p_profile_read": [_vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)],
+    "lbm2p_adjoint_workspace_bytes": [ctypes.POINTER(Params), ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_size_t)],
+    "lbm2p_record": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t],
+    "lbm2p_adjoint": [_vp, ctypes.POINTER(AdjointIO)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -166,6 +180,23 @@ def lbm2p_profile_read(ctx):
     return ms.value, n.value
 
 
+def lbm2p_adjoint_workspace_bytes(p, nsteps, ckpt_every):
+    n = ctypes.c_size_t(0)
+    _check(_lib.lbm2p_adjoint_workspace_bytes(ctypes.byref(p), int(nsteps), int(ckpt_every),
+                                              ctypes.byref(n)), "lbm2p_adjoint_workspace_bytes")
+    return n.value
+
+
+def lbm2p_record(ctx, nsteps, ckpt_every, ws_ptr, nbytes):
+    _check(_lib.lbm2p_record(ctx, int(nsteps), int(ckpt_every), _vp(ws_ptr), nbytes),
+           "lbm2p_record")
+
+
+def lbm2p_adjoint(ctx, io):
+    _check(_lib.lbm2p_adjoint(ctx, ctypes.byref(io)), "lbm2p_adjoint")
+    return io.dL_dsigma, io.dL_dM
+
+
 def lbm2p_destroy(ctx):
     _lib.lbm2p_destroy(ctx)
 
@@ -243,6 +274,43 @@ class Sim:
         self.torch.cuda.current_stream(self.device).synchronize()
         return self
 
+    def record(self, nsteps, ckpt_every=64):
+        """Advance nsteps steps keeping the checkpoints the adjoint needs."""
+        nbytes = lbm2p_adjoint_workspace_bytes(self.p, nsteps, ckpt_every)
+        self.adj_ws = self.torch.empty(nbytes + 256, dtype=self.torch.uint8, device=self.device)
+        aligned = (self.adj_ws.data_ptr() + 255) // 256 * 256
+        lbm2p_record(self.ctx, nsteps, ckpt_every, aligned, nbytes)
+        return self
+
+    def adjoint(self, dL_dphi=None, dL_df=None, dL_dg=None, dL_du=None, want_phi0=False,
+                want_state=False):
+        """Reverse mode of the last record(): seeds on the final phi / state,
+        returns dL/dsigma, dL/dM and (on request) dL/dphi0 and the adjoint of
+        the recorded run's initial state."""
+        t = self.torch
+        seeds = [self._dev(a) for a in (dL_dphi, dL_df, dL_dg, dL_du)]
+        io = AdjointIO()
+        for name, a in zip(("dL_dphi", "dL_df", "dL_dg", "dL_du"), seeds):
+            setattr(io, name, a.data_ptr() if a is not None else None)
+        out = {}
+        if want_phi0:
+            phi0, ux0, uy0 = self._keep[0], self._keep[1], self._keep[2]
+            io.phi0 = phi0.data_ptr()
+            io.ux0 = ux0.data_ptr() if ux0 is not None else None
+            io.uy0 = uy0.data_ptr() if uy0 is not None else None
+            out["phi0"] = self._plane()
+            io.dL_dphi0 = out["phi0"].data_ptr()
+        if want_state:
+            out["f0"] = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
+            io.dL_df0 = out["f0"].data_ptr()
+            if self.coupled:
+                out["g0"] = t.empty((9, self.ny, self.nx), dtype=t.float64, device=self.device)
+                io.dL_dg0 = out["g0"].data_ptr()
+            out["u0"] = t.empty((2, self.ny, self.nx), dtype=t.float64, device=self.device)
+            io.dL_du0 = out["u0"].data_ptr()
+        out["sigma"], out["M"] = lbm2p_adjoint(self.ctx, io)
+        return out
+
     def profile(self, pass_name):
         lbm2p_profile(self.ctx, -1 if pass_name is None else PASSES[pass_name])
 
@@ -259,3 +327,50 @@ class Sim:
             self.close()
         except Exception:
             pass
+
+
+def _autograd_function():
+    import torch
+
+    class PhaseFieldRun(torch.autograd.Function):
+        """(sigma, M, phi0) -> phi after nsteps steps, with the HIP adjoint as
+        its backward (checkpoints every ckpt_every steps).  sigma and M are
+        0-dim float64 tensors, phi0 a (ny, nx) float64 tensor; params holds
+        every other parameter; ux0, uy0, p0 are constants."""
+
+        @staticmethod
+        def forward(ctx, sigma, M, phi0, params, nsteps, ckpt_every=64, precision=0, ux0=None,
+                    uy0=None, p0=None):
+            prm = dict(params)
+            prm["sigma"] = float(sigma)
+            prm["M"] = float(M)
+            dev = phi0.device if phi0.is_cuda else torch.device("cuda:0")
+            sim = Sim(prm, precision=precision, device=dev)
+            sim.init(phi0.detach(), ux0, uy0, p0)
+            sim.record(nsteps, ckpt_every)
+            ctx.sim = sim
+            return sim.moments()["phi"].to(phi0.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            sim = ctx.sim
+            out = sim.adjoint(dL_dphi=g, want_phi0=True)
+            ctx.sim = None
+            sim.close()
+            dt = torch.float64
+            return (torch.tensor(out["sigma"], dtype=dt), torch.tensor(out["M"], dtype=dt),
+                    out["phi0"].to(g.device), None, None, None, None, None, None, None)
+
+    return PhaseFieldRun
+
+
+def phase_field_run(sigma, M, phi0, params, nsteps, ckpt_every=64, precision=0, ux0=None,
+                    uy0=None, p0=None):
+    """Differentiable run: phi_T as a function of (sigma, M, phi0)."""
+    global _PFR
+    if _PFR is None:
+        _PFR = _autograd_function()
+    return _PFR.apply(sigma, M, phi0, params, nsteps, ckpt_every, precision, ux0, uy0, p0)
+
+
+_PFR = None

@@ -265,6 +265,10 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   c->prof_pass = -1;
   c->prof_n = 0;
   c->inited = 0;
+  c->rec = 0;
+  c->from_init = 0;
+  c->adj_ready = 0;
+  c->adj_ws = nullptr;
   *out = c;
   return LBM2P_OK;
 }
@@ -286,7 +290,38 @@ int lbm2p_init_fields(lbm2p_ctx* c, const double* phi0, const double* ux0, const
 int lbm2p_step(lbm2p_ctx* c, int32_t n) {
   if (!c || n < 0) return LBM2P_EINVAL;
   if (!c->inited) return LBM2P_ESTATE;
+  if (n > 0) c->adj_ready = 0;
   return c->prec ? step_f32(c, n) : step_f64(c, n);
+}
+
+int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t ckpt_every,
+                                  size_t* bytes) {
+  const int e = validate(p);
+  if (e) return e;
+  if (!bytes || nsteps < 0 || ckpt_every < 1 || p->compact) return LBM2P_EINVAL;
+  const AdjLayout L = adj_layout(*p, plane_stride(p), (long long)p->nx * p->ny,
+                                 p->precision ? 4 : 8, nsteps, ckpt_every);
+  *bytes = L.total;
+  return LBM2P_OK;
+}
+
+int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes) {
+  if (!c || nsteps < 0 || ckpt_every < 1 || !d_ws || ((uintptr_t)d_ws & 255)) return LBM2P_EINVAL;
+  if (c->p.compact) return LBM2P_EINVAL;
+  if (!c->inited) return LBM2P_ESTATE;
+  const AdjLayout L = adj_layout(c->p, c->ps, c->n, c->esz, nsteps, ckpt_every);
+  if (bytes < L.total) return LBM2P_ENOSPACE;
+  c->adj_ws = (char*)d_ws;
+  c->adj_bytes = bytes;
+  return c->prec ? record_f32(c, nsteps, ckpt_every) : record_f64(c, nsteps, ckpt_every);
+}
+
+int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
+  if (!c || !io) return LBM2P_EINVAL;
+  if (!c->inited || !c->adj_ready || c->steps != c->adj_steps_end) return LBM2P_ESTATE;
+  if (io->dL_dphi0 && !io->phi0) return LBM2P_EINVAL;
+  if (io->dL_dphi0 && !c->adj_from_init) return LBM2P_ESTATE;
+  return c->prec ? adjoint_f32(c, io) : adjoint_f64(c, io);
 }
 
 int lbm2p_moments(lbm2p_ctx* c, double* phi, double* ux, double* uy, double* p, double* rho) {

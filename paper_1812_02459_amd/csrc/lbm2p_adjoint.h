@@ -1,0 +1,962 @@
+// Reverse-mode (adjoint) kernels of one lattice update (gfx950).
+//
+// The forward step is a chain of stencils over the ghost extension of a field
+// (periodic wrap or half-way mirror, sign kept or flipped per field) and
+// pointwise maps.  Every intermediate of the forward step is mirror-equivariant
+// (a value computed at a ghost equals the mirror node's value times the field's
+// parity), so the step is the same function of the real nodes as one that
+// keeps each intermediate on the real nodes only and extends it when a stencil
+// reads it.  The adjoint therefore works on real-node planes throughout:
+//   * a pointwise map is reversed at its node with the Jacobian at the
+//     recomputed forward values;
+//   * a stencil O = S(ext X) is reversed in gather form,
+//       X_bar(y) = sum over the images z of y  s(z) sum_o c_o O_bar(z - o),
+//     where the images of y are y itself and its mirror nodes beyond each wall
+//     (within the stencil radius), s(z) the parity sign of the stencil's input
+//     X under the mirrors that map z to y, and O_bar is zero beyond a wall and
+//     wraps along a periodic axis.
+// No atomics: every output element is written by one thread, so the adjoint is
+// deterministic.  Parameter derivatives (sigma, M) are accumulated per node in
+// float64 planes and reduced once at the end.
+//
+// Parities (sign under the x-mirror, the y-mirror): phi, mu, rho, p (+,+);
+// u_x, u_y (-,-) (no-slip ghosts flip every component); d/dx of an even field
+// (-,+), d/dy (+,-); (d_x phi)^2, (d_y phi)^2 (+,+); d_x phi d_y phi (-,-).
+#pragma once
+
+#include "lbm2p_kernels.h"
+
+namespace lbm2p {
+
+// derivatives of the derived constants with respect to sigma and M
+// (kappa = 3 sigma W / 8, 4 beta = 3 sigma / W, eta = 3 M / (tau_f - 1/2),
+// c_J = (rho1 - rho2) M / 2, -M in q)
+struct AdjConst {
+  double dc4b, dkap, deta, dcJ;  // d/dsigma of 4 beta and kappa; d/dM of eta and c_J
+  double c4b, kappa;             // 4 beta and kappa in float64 (initial state)
+};
+
+// ------------------------------------------------------------ plane readers
+// adjoint plane: zero beyond a wall, periodic wrap otherwise
+template <typename T>
+struct ZRead {
+  const T* a;
+  int nx, ny, wx, wy;
+  __device__ __forceinline__ T operator()(int x, int y) const {
+    if (x < 0 || x >= nx) {
+      if (wx) return T(0);
+      x = x < 0 ? x + nx : x - nx;
+    }
+    if (y < 0 || y >= ny) {
+      if (wy) return T(0);
+      y = y < 0 ? y + ny : y - ny;
+    }
+    return a[(long long)y * nx + x];
+  }
+};
+
+// forward plane through the ghost extension (mirror with parity, or wrap)
+template <typename T>
+struct ERead {
+  const T* a;
+  int nx, ny, wx, wy;
+  bool odd;
+  __device__ __forceinline__ T operator()(int x, int y) const {
+    int flip = 0;
+    const int xx = map_idx(x, nx, wx, flip);
+    const int yy = map_idx(y, ny, wy, flip);
+    const T v = a[(long long)yy * nx + xx];
+    return (odd && flip) ? -v : v;
+  }
+};
+
+template <typename T>
+__device__ __forceinline__ ZRead<T> zread(const T* a, const KParams<T>& P) {
+  return ZRead<T>{a, P.nx, P.ny, P.wx, P.wy};
+}
+template <typename T>
+__device__ __forceinline__ ERead<T> eread(const T* a, const KParams<T>& P, bool odd) {
+  return ERead<T>{a, P.nx, P.ny, P.wx, P.wy, odd};
+}
+
+// Sum of op(z) over the images z of node (x, y) within depth R of a wall,
+// each with the product of the parity signs (sx, sy) of its mirrored axes.
+template <typename T, int R, typename Op>
+__device__ __forceinline__ T fold(const KParams<T>& P, int x, int y, int sx, int sy, Op op) {
+  int ix[3], iy[3], gx[3], gy[3];
+  int ncx = 1, ncy = 1;
+  ix[0] = x;
+  gx[0] = 1;
+  iy[0] = y;
+  gy[0] = 1;
+  if (P.wx) {
+    if (x < R) { ix[ncx] = -1 - x; gx[ncx++] = sx; }
+    if (x >= P.nx - R) { ix[ncx] = 2 * P.nx - 1 - x; gx[ncx++] = sx; }
+  }
+  if (P.wy) {
+    if (y < R) { iy[ncy] = -1 - y; gy[ncy++] = sy; }
+    if (y >= P.ny - R) { iy[ncy] = 2 * P.ny - 1 - y; gy[ncy++] = sy; }
+  }
+  T acc = op(x, y);
+  for (int a = 0; a < ncx; ++a)
+    for (int b = 0; b < ncy; ++b) {
+      if (a == 0 && b == 0) continue;
+      const T v = op(ix[a], iy[b]);
+      acc = (gx[a] * gy[b] > 0) ? acc + v : acc - v;
+    }
+  return acc;
+}
+
+// transposed stencils at an extended position, reading a ZRead
+// (iso_grad and d4 are antisymmetric, iso_lap and the filter symmetric)
+template <typename T>
+struct GradXT {
+  ZRead<T> r;
+  __device__ __forceinline__ T operator()(int x, int y) const { return -iso_grad_x<T>(r, x, y); }
+};
+template <typename T>
+struct GradYT {
+  ZRead<T> r;
+  __device__ __forceinline__ T operator()(int x, int y) const { return -iso_grad_y<T>(r, x, y); }
+};
+// sum of the transposed x-gradient of a and the transposed y-gradient of b
+template <typename T>
+struct DivT {
+  ZRead<T> a, b;
+  __device__ __forceinline__ T operator()(int x, int y) const {
+    return -(iso_grad_x<T>(a, x, y) + iso_grad_y<T>(b, x, y));
+  }
+};
+template <typename T>
+struct LapT {
+  ZRead<T> r;
+  __device__ __forceinline__ T operator()(int x, int y) const { return iso_lap<T>(r, x, y); }
+};
+template <typename T>
+struct D4XT {
+  ZRead<T> r;
+  __device__ __forceinline__ T operator()(int x, int y) const {
+    return -d4<T>(r(x - 2, y), r(x - 1, y), r(x + 1, y), r(x + 2, y));
+  }
+};
+template <typename T>
+struct D4YT {
+  ZRead<T> r;
+  __device__ __forceinline__ T operator()(int x, int y) const {
+    return -d4<T>(r(x, y - 2), r(x, y - 1), r(x, y + 1), r(x, y + 2));
+  }
+};
+template <typename T, int N>
+struct FilterT {
+  ZRead<T> r;
+  const T* d;
+  __device__ __forceinline__ T operator()(int x, int y) const {
+    T sx = d[N] * r(x - N, y);
+#pragma unroll
+    for (int j = -N + 1; j <= N; ++j) sx = sx + d[j < 0 ? -j : j] * r(x + j, y);
+    T sy = d[N] * r(x, y - N);
+#pragma unroll
+    for (int j = -N + 1; j <= N; ++j) sy = sy + d[j < 0 ? -j : j] * r(x, y + j);
+    return sx + sy;
+  }
+};
+
+// ------------------------------------------------------- pointwise adjoints
+// (M^T v)_i = sum_k M_ki v_k
+template <typename T>
+__device__ __forceinline__ void mT_apply(const T v[9], T out[9]) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    T acc = T(0);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+      const int c = mrt(k, i);
+      if (c == 0) continue;
+      acc = acc + T(c) * v[k];
+    }
+    out[i] = acc;
+  }
+}
+
+// Reverse of f* = f + M^-1 [ (I - S/2) M F - S M (f - f^eq) ] given the
+// adjoint y of f*:  r = diag(1/(M M^T)_kk) M y,  f_bar = y - M^T (S r),
+// feq_bar = M^T (S r),  F_bar = M^T ((I - S/2) r).  r is returned for the
+// derivative with respect to a relaxation rate: s_k_bar = r_k (-mF_k/2 - md_k).
+template <typename T>
+__device__ __forceinline__ void mrt_collide_adj(const T y[9], const T s[9], T fbar[9], T feqb[9],
+                                                T Fb[9], T r[9]) {
+  T my[9], sr[9], hr[9];
+  m_apply(y, my);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    r[k] = my[k] * T(mm_inv(k));
+    sr[k] = s[k] * r[k];
+    hr[k] = (T(1) - s[k] * T(0.5)) * r[k];
+  }
+  mT_apply(sr, feqb);
+  mT_apply(hr, Fb);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fbar[i] = y[i] - feqb[i];
+}
+
+// reverse of f_eq (eq:feq_CH): adds to phb, mub, ubx, uby, etab
+template <typename T>
+__device__ __forceinline__ void f_eq_adj(T phi, T mu, T ux, T uy, T eta, const T fb[9], T& phb,
+                                         T& mub, T& ubx, T& uby, T& etab) {
+  const T usq = ux * ux + uy * uy;
+  const T w0 = T(w_of(0));
+  phb = phb + fb[0] * (T(1) - (w0 * usq) * T(1.5));
+  mub = mub + fb[0] * ((w0 - T(1)) * eta);
+  etab = etab + fb[0] * ((w0 - T(1)) * mu);
+  T usqb = -(fb[0] * (w0 * phi)) * T(1.5);
+  T cx = T(0), cy = T(0);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const T w = T(w_of(i));
+    const T cu = cdot(i, ux, uy);
+    const T inner = ((cu * T(3)) + ((cu * cu) * T(4.5))) - usq * T(1.5);
+    const T a = fb[i] * w;
+    phb = phb + a * inner;
+    mub = mub + a * eta;
+    etab = etab + a * mu;
+    const T ap = a * phi;
+    usqb = usqb - ap * T(1.5);
+    const T cub = ap * (T(3) + cu * T(9));
+    if (cx_of(i)) cx = cx_of(i) > 0 ? cx + cub : cx - cub;
+    if (cy_of(i)) cy = cy_of(i) > 0 ? cy + cub : cy - cub;
+  }
+  ubx = ubx + (cx + (usqb * T(2)) * ux);
+  uby = uby + (cy + (usqb * T(2)) * uy);
+}
+
+// reverse of g_eq (eq:geq): adds to pb, ubx, uby
+template <typename T>
+__device__ __forceinline__ void g_eq_adj(T ux, T uy, const T gb[9], T& pb, T& ubx, T& uby) {
+  T usqb = T(0), cx = T(0), cy = T(0), sp = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T a = gb[i] * T(w_of(i));
+    sp = sp + a;
+    usqb = usqb - a * T(1.5);
+    const T cu = cdot(i, ux, uy);
+    const T cub = a * (T(3) + cu * T(9));
+    if (cx_of(i)) cx = cx_of(i) > 0 ? cx + cub : cx - cub;
+    if (cy_of(i)) cy = cy_of(i) > 0 ? cy + cub : cy - cub;
+  }
+  pb = pb + sp * T(3);
+  ubx = ubx + (cx + (usqb * T(2)) * ux);
+  uby = uby + (cy + (usqb * T(2)) * uy);
+}
+
+// reverse of src_f (eq:Fi): adds to phb, abx, aby
+template <typename T>
+__device__ __forceinline__ void src_f_adj(T phi, T ax, T ay, const T Fb[9], T& phb, T& abx,
+                                          T& aby) {
+  T cx = T(0), cy = T(0);
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const T a = (Fb[i] * T(w_of(i))) * T(3);
+    phb = phb + a * cdot(i, ax, ay);
+    const T ap = a * phi;
+    if (cx_of(i)) cx = cx_of(i) > 0 ? cx + ap : cx - ap;
+    if (cy_of(i)) cy = cy_of(i) > 0 ? cy + ap : cy - ap;
+  }
+  abx = abx + cx;
+  aby = aby + cy;
+}
+
+// reverse of src_g (eq:Gi, b = F/rho - grad p): adds to Frb, ub, bb
+template <typename T>
+__device__ __forceinline__ void src_g_adj(T ux, T uy, T bx, T by, const T Gb[9], T& Frbx,
+                                          T& Frby, T& ubx, T& uby, T& bbx, T& bby) {
+  T ubb = T(0), fx = T(0), fy = T(0), ux_ = T(0), uy_ = T(0), bx_ = T(0), by_ = T(0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T a = Gb[i] * T(w_of(i));
+    ubb = ubb - a * T(3);
+    if (i == 0) continue;
+    const T cu = cdot(i, ux, uy), cb = cdot(i, bx, by);
+    const T cfb = a * T(3), cub = (a * T(9)) * cb, cbb = (a * T(9)) * cu;
+    if (cx_of(i)) {
+      const bool p = cx_of(i) > 0;
+      fx = p ? fx + cfb : fx - cfb;
+      ux_ = p ? ux_ + cub : ux_ - cub;
+      bx_ = p ? bx_ + cbb : bx_ - cbb;
+    }
+    if (cy_of(i)) {
+      const bool p = cy_of(i) > 0;
+      fy = p ? fy + cfb : fy - cfb;
+      uy_ = p ? uy_ + cub : uy_ - cub;
+      by_ = p ? by_ + cbb : by_ - cbb;
+    }
+  }
+  Frbx = Frbx + fx;
+  Frby = Frby + fy;
+  ubx = ubx + (ux_ + ubb * bx);
+  uby = uby + (uy_ + ubb * by);
+  bbx = bbx + (bx_ + ubb * ux);
+  bby = bby + (by_ + ubb * uy);
+}
+
+// rho, nu from clamp(phi) (eq:rho, eq:dynamic_vis): phi_bar from rho_bar, nu_bar.
+// The clamp passes the derivative for -1 <= phi <= 1 (ends included).
+template <typename T>
+__device__ __forceinline__ T props_adj(T phi, T rho, T nu, T rhob, T nub, const KParams<T>& P) {
+  if (!(phi >= T(-1) && phi <= T(1))) return T(0);
+  const T rb = rhob - (nub * nu) / rho;
+  const T mb = nub / rho;
+  return rb * ((P.rho1 - P.rho2) / T(2)) + mb * ((P.mu1 - P.mu2) / T(2));
+}
+
+// forward internals of the force at a tile node (same arithmetic as node_force)
+template <typename T>
+struct ForceFwd {
+  T Fx, Fy, rho, nu;
+  T grx, gry;                 // isotropic gradient of rho(clamp phi)
+  T du[4];                    // d ux/dx, d ux/dy, d uy/dx, d uy/dy
+  T dmx, dmy;                 // isotropic gradient of mu
+  T Q[4];                     // d_x(py^2), d_x(px py), d_y(px py), d_y(px^2)
+};
+
+template <typename T>
+__device__ __forceinline__ void force_fwd(const Tile<T>& tP, const Tile<T>& tPx, const Tile<T>& tPy,
+                                          const Tile<T>& tMu, const Tile<T>& tRho,
+                                          const Tile<T>& tUx, const Tile<T>& tUy, T p, int x, int y,
+                                          const KParams<T>& P, ForceFwd<T>& f) {
+  const T phi = tP(x, y);
+  f.rho = density<T>(phi, P.rho1, P.rho2);
+  f.nu = kin_visc<T>(phi, f.rho, P.mu1, P.mu2);
+  iso_grad<T>(tMu, x, y, f.dmx, f.dmy);
+  const T Jx = P.cJ * f.dmx, Jy = P.cJ * f.dmy;
+  f.Q[0] = iso_grad_x<T>(ProdYY<T>{tPy}, x, y);
+  iso_grad<T>(ProdXY<T>{tPx, tPy}, x, y, f.Q[1], f.Q[2]);
+  f.Q[3] = iso_grad_y<T>(ProdXX<T>{tPx}, x, y);
+  const T Fsx = P.kappa * (f.Q[0] - f.Q[2]);
+  const T Fsy = P.kappa * (f.Q[3] - f.Q[1]);
+  iso_grad<T>(tRho, x, y, f.grx, f.gry);
+  iso_grad<T>(tUx, x, y, f.du[0], f.du[1]);
+  iso_grad<T>(tUy, x, y, f.du[2], f.du[3]);
+  const T Fpx = (-p) * f.grx, Fpy = (-p) * f.gry;
+  const T Sxx = f.du[0] + f.du[0], Sxy = f.du[2] + f.du[1], Syy = f.du[3] + f.du[3];
+  const T Fnx = f.nu * (Sxx * f.grx + Sxy * f.gry);
+  const T Fny = f.nu * (Sxy * f.grx + Syy * f.gry);
+  const T Fmx = Jx * f.du[0] + Jy * f.du[1];
+  const T Fmy = Jx * f.du[2] + Jy * f.du[3];
+  const T Fgx = (f.rho - P.rho_ref) * P.gx;
+  const T Fgy = (f.rho - P.rho_ref) * P.gy;
+  f.Fx = (((Fpx + Fsx) + Fnx) + Fmx) + Fgx;
+  f.Fy = (((Fpy + Fsy) + Fny) + Fmy) + Fgy;
+}
+
+// adjoint of the force given F_bar; every field is an output (written)
+template <typename T>
+struct ForceAdj {
+  T p, grx, gry, du[4], dmx, dmy, Q[4], rho, nu, kappa, cJ;
+};
+
+template <typename T>
+__device__ __forceinline__ void force_adj(const ForceFwd<T>& f, T p, T Fbx, T Fby,
+                                          const KParams<T>& P, ForceAdj<T>& a) {
+  // F_p = -p grad rho
+  a.p = -(Fbx * f.grx + Fby * f.gry);
+  T grx = -(p * Fbx), gry = -(p * Fby);
+  // F_s = kappa (d_x(py^2) - d_y(px py), d_y(px^2) - d_x(px py))
+  a.kappa = Fbx * (f.Q[0] - f.Q[2]) + Fby * (f.Q[3] - f.Q[1]);
+  a.Q[0] = P.kappa * Fbx;
+  a.Q[2] = -(P.kappa * Fbx);
+  a.Q[3] = P.kappa * Fby;
+  a.Q[1] = -(P.kappa * Fby);
+  // F_nu = nu (grad u + grad u^T) . grad rho
+  const T Sxx = f.du[0] + f.du[0], Sxy = f.du[2] + f.du[1], Syy = f.du[3] + f.du[3];
+  a.nu = Fbx * (Sxx * f.grx + Sxy * f.gry) + Fby * (Sxy * f.grx + Syy * f.gry);
+  grx = grx + f.nu * (Fbx * Sxx + Fby * Sxy);
+  gry = gry + f.nu * (Fbx * Sxy + Fby * Syy);
+  const T Sbxx = f.nu * (Fbx * f.grx), Sbxy = f.nu * (Fbx * f.gry + Fby * f.grx),
+          Sbyy = f.nu * (Fby * f.gry);
+  // F_m = (J . grad) u with J = c_J grad mu
+  const T Jx = P.cJ * f.dmx, Jy = P.cJ * f.dmy;
+  const T Jbx = Fbx * f.du[0] + Fby * f.du[2];
+  const T Jby = Fbx * f.du[1] + Fby * f.du[3];
+  a.du[0] = (Sbxx + Sbxx) + Jx * Fbx;
+  a.du[1] = Sbxy + Jy * Fbx;
+  a.du[2] = Sbxy + Jx * Fby;
+  a.du[3] = (Sbyy + Sbyy) + Jy * Fby;
+  a.dmx = P.cJ * Jbx;
+  a.dmy = P.cJ * Jby;
+  a.cJ = Jbx * f.dmx + Jby * f.dmy;
+  // F_g = (rho - rho_ref) g
+  a.rho = Fbx * P.gx + Fby * P.gy;
+  a.grx = grx;
+  a.gry = gry;
+}
+
+// canonical index of the post-collision population that streams into
+// f_i(x, y) (x - c_i, or the node itself with opp(i) beyond a wall)
+template <typename T>
+__device__ __forceinline__ long long src_slot(const KParams<T>& P, int i, int x, int y) {
+  const int cx = cx_of(i), cy = cy_of(i);
+  int sx = x - cx, sy = y - cy;
+  const bool out = (P.wx && (sx < 0 || sx >= P.nx)) || (P.wy && (sy < 0 || sy >= P.ny));
+  if (out) return (long long)opp(i) * P.ps + (long long)y * P.nx + x;
+  sx = sx < 0 ? sx + P.nx : (sx >= P.nx ? sx - P.nx : sx);
+  sy = sy < 0 ? sy + P.ny : (sy >= P.ny ? sy - P.ny : sy);
+  return (long long)i * P.ps + (long long)sy * P.nx + sx;
+}
+
+// work planes of the reverse step
+template <typename T>
+struct AdjWork {
+  T *lp_p, *lp_ux, *lp_uy, *dp_x, *dp_y;   // collision: local p, u adjoints, grad p adjoint
+  T* du[2][4];                             // grad u adjoints (ping-pong)
+  T *a_phi, *a_mu, *a_grx, *a_gry, *a_dmx, *a_dmy, *a_Q[4];  // phi-side accumulators
+  T *mu_b, *rho_b, *px_b, *py_b;           // transposed phi-side intermediates
+  T *pt_b, *utx_b, *uty_b, *ukx_b, *uky_b;  // filtered p, u adjoints; u^K adjoint
+  T *praw_b, *jx_b, *jy_b;
+  T *phi_b, *phi2_b, *phi1_b, *phib_b;     // adjoints of phi^{n+1}, phi^(2), phi^(1), phi_bar
+  T *fd_gx, *fd_gy, *fd_mx, *fd_my, *fd_loc, *fd_mu;
+  double *sig, *dM;                        // per-node partials of dL/dsigma, dL/dM
+};
+
+template <typename T>
+__device__ __forceinline__ T* du_sel(const AdjWork<T>& W, int s, int k) {
+  return s ? W.du[1][k] : W.du[0][k];
+}
+
+// ------------------------------------------------------- a5^T: collision
+// Local adjoint of the collision at every node.  Writes the adjoint of the
+// pre-collision populations to the canonical slot they streamed from (the
+// streaming permutation reversed), the local p and u adjoints, the grad u and
+// grad p adjoints, and initialises the phi-side accumulators.
+template <typename T, bool COUPLED, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adj_collide(
+    KParams<T> P, AdjConst C, int tiles_x, const T* __restrict__ phi, const T* __restrict__ pt,
+    const T* __restrict__ ux, const T* __restrict__ uy, const T* __restrict__ uox,
+    const T* __restrict__ uoy, const T* __restrict__ m7g, const T* __restrict__ m8g,
+    const T* __restrict__ Afi, const T* __restrict__ Agi, T* __restrict__ Afo, T* __restrict__ Ago,
+    T* __restrict__ Uox, T* __restrict__ Uoy, AdjWork<T> Wk) {
+  constexpr int NT = 256;
+  constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  __shared__ T sP[W2 * H2];
+  __shared__ T sPx[COUPLED ? W1 * H1 : 1], sPy[COUPLED ? W1 * H1 : 1], sMu[W1 * H1],
+      sRho[COUPLED ? W1 * H1 : 1], sUx[W1 * H1], sUy[W1 * H1], sPt[COUPLED ? W1 * H1 : 1];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
+  load_window<T, T, NT>(sUx, W1, H1, ux, x0 - 1, y0 - 1, P, true);
+  load_window<T, T, NT>(sUy, W1, H1, uy, x0 - 1, y0 - 1, P, true);
+  if (COUPLED) load_window<T, T, NT>(sPt, W1, H1, pt, x0 - 1, y0 - 1, P, false);
+  __syncthreads();
+  const Tile<T> tP{sP, W2, 2};
+  if (COUPLED) {
+    derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
+  } else {
+    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
+      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+      sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
+    }
+  }
+  __syncthreads();
+  const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
+      tUx{sUx, W1, 1}, tUy{sUy, W1, 1}, tPt{sPt, W1, 1};
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int ly = idx / TX, lx = idx % TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) continue;
+    const long long id = (long long)y * P.nx + x;
+    const T ph = tP(lx, ly), u_x = tUx(lx, ly), u_y = tUy(lx, ly);
+    T duxx, duxy, duyx, duyy;
+    iso_grad<T>(tUx, lx, ly, duxx, duxy);
+    iso_grad<T>(tUy, lx, ly, duyx, duyy);
+    const T ax = (u_x - uox[id]) + (u_x * duxx + u_y * duxy);
+    const T ay = (u_y - uoy[id]) + (u_x * duyx + u_y * duyy);
+    const T mu = tMu(lx, ly);
+    T phb = T(0), mub = T(0), ubx = T(0), uby = T(0), etab = T(0), abx = T(0), aby = T(0);
+    {
+      T yv[9], fb[9], feqb[9], Fb[9], r[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) yv[i] = Afi[i * P.ps + id];
+      mrt_collide_adj<T>(yv, P.s_f, fb, feqb, Fb, r);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Afo[src_slot(P, i, x, y)] = fb[i];
+      f_eq_adj<T>(ph, mu, u_x, u_y, P.eta, feqb, phb, mub, ubx, uby, etab);
+      src_f_adj<T>(ph, ax, ay, Fb, phb, abx, aby);
+    }
+    double dM = double(etab) * C.deta;
+    if (COUPLED) {
+      // accel reversed: a = (u - u_o) + (u . grad) u
+      ubx = ubx + (abx + (abx * duxx + aby * duyx));
+      uby = uby + (aby + (abx * duxy + aby * duyy));
+      Uox[id] = -abx;
+      Uoy[id] = -aby;
+      T dub[4] = {abx * u_x, abx * u_y, aby * u_x, aby * u_y};
+      const T p = tPt(lx, ly);
+      ForceFwd<T> ff;
+      force_fwd<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, lx, ly, P, ff);
+      T dpx, dpy;
+      iso_grad<T>(tPt, lx, ly, dpx, dpy);
+      const T Frx = ff.Fx / ff.rho, Fry = ff.Fy / ff.rho;
+      const T bxv = Frx - dpx, byv = Fry - dpy;
+      T geq[9], G[9], s[9], mG[9], mq[9];
+      g_eq<T>(p, u_x, u_y, geq);
+      src_g<T>(Frx, Fry, u_x, u_y, bxv, byv, G);
+      const T tau_g = ff.nu * T(3) + T(0.5);
+      const T sv = T(1) / tau_g;
+#pragma unroll
+      for (int k = 0; k < 9; ++k) s[k] = P.s_g[k];
+      s[7] = sv;
+      s[8] = sv;
+      m_apply(G, mG);
+      m_apply(geq, mq);
+      const T md7 = m7g[id] - mq[7], md8 = m8g[id] - mq[8];
+      T yv[9], gb[9], geqb[9], Gb[9], r[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) yv[i] = Agi[i * P.ps + id];
+      mrt_collide_adj<T>(yv, s, gb, geqb, Gb, r);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) Ago[src_slot(P, i, x, y)] = gb[i];
+      const T svb = r[7] * (-(mG[7] * T(0.5)) - md7) + r[8] * (-(mG[8] * T(0.5)) - md8);
+      const T nub = -((svb * T(3)) * (sv * sv));
+      T pb = T(0), Frbx = T(0), Frby = T(0), bbx = T(0), bby = T(0);
+      g_eq_adj<T>(u_x, u_y, geqb, pb, ubx, uby);
+      src_g_adj<T>(u_x, u_y, bxv, byv, Gb, Frbx, Frby, ubx, uby, bbx, bby);
+      Frbx = Frbx + bbx;
+      Frby = Frby + bby;
+      const T Fbx = Frbx / ff.rho, Fby = Frby / ff.rho;
+      const T rhob = -((Frbx * Frx + Frby * Fry) / ff.rho);
+      ForceAdj<T> fa;
+      force_adj<T>(ff, p, Fbx, Fby, P, fa);
+      pb = pb + fa.p;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dub[k] = dub[k] + fa.du[k];
+      phb = phb + props_adj<T>(ph, ff.rho, ff.nu, fa.rho + rhob, fa.nu + nub, P);
+      Wk.lp_p[id] = pb;
+      Wk.lp_ux[id] = ubx;
+      Wk.lp_uy[id] = uby;
+      Wk.dp_x[id] = -bbx;
+      Wk.dp_y[id] = -bby;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Wk.du[0][k][id] = dub[k];
+      Wk.a_grx[id] = fa.grx;
+      Wk.a_gry[id] = fa.gry;
+      Wk.a_dmx[id] = fa.dmx;
+      Wk.a_dmy[id] = fa.dmy;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) Wk.a_Q[k][id] = fa.Q[k];
+      Wk.sig[id] = Wk.sig[id] + double(fa.kappa) * C.dkap;
+      dM = dM + double(fa.cJ) * C.dcJ;
+    }
+    Wk.a_phi[id] = phb;
+    Wk.a_mu[id] = mub;
+    Wk.dM[id] = Wk.dM[id] + dM;
+  }
+}
+
+// Transposed gradients of the collision: adjoints of the filtered u and p.
+// u~ is also the next state's velocity, whose adjoint Uoi adds here.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_collide_t(KParams<T> P, const T* __restrict__ Uoix,
+                                                       const T* __restrict__ Uoiy, AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T gux = fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(Wk.du[0][0], P), zread(Wk.du[0][1], P)});
+  const T guy = fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(Wk.du[0][2], P), zread(Wk.du[0][3], P)});
+  const T gp = fold<T, 1>(P, x, y, 1, 1, DivT<T>{zread(Wk.dp_x, P), zread(Wk.dp_y, P)});
+  Wk.utx_b[id] = (Wk.lp_ux[id] + gux) + Uoix[id];
+  Wk.uty_b[id] = (Wk.lp_uy[id] + guy) + Uoiy[id];
+  Wk.pt_b[id] = Wk.lp_p[id] + gp;
+}
+
+// ---------------------------------------------------------- a4^T: filter
+// chi_bar = chi~_bar - a F^T chi~_bar (the explicit filter's stencil is
+// symmetric); N = 0: the identity.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_adj_filter(KParams<T> P, AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  if (N == 0) {
+    Wk.praw_b[id] = Wk.pt_b[id];
+    Wk.ukx_b[id] = Wk.utx_b[id];
+    Wk.uky_b[id] = Wk.uty_b[id];
+    return;
+  }
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T a = P.fa;
+  const T sp = fold<T, N>(P, x, y, 1, 1, FilterT<T, N>{zread(Wk.pt_b, P), P.fd});
+  const T sx = fold<T, N>(P, x, y, -1, -1, FilterT<T, N>{zread(Wk.utx_b, P), P.fd});
+  const T sy = fold<T, N>(P, x, y, -1, -1, FilterT<T, N>{zread(Wk.uty_b, P), P.fd});
+  Wk.praw_b[id] = Wk.pt_b[id] - a * sp;
+  Wk.ukx_b[id] = Wk.utx_b[id] - a * sx;
+  Wk.uky_b[id] = Wk.uty_b[id] - a * sy;
+}
+
+// -------------------------------------------- a3^T: one velocity sweep
+// Reverse of u^{k+1} = j + F(u^k)/(2 rho).  The adjoint of u^{k+1} is the
+// filter's output for the last sweep (FIRST), else the transposed gradient of
+// the previous reverse sweep's grad-u adjoint (du[src]); this sweep writes its
+// own grad-u adjoint to du[1 - src].
+template <typename T, bool FIRST, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int tiles_x,
+                                                 const T* __restrict__ phi,
+                                                 const T* __restrict__ praw,
+                                                 const T* __restrict__ ukx,
+                                                 const T* __restrict__ uky, int src,
+                                                 AdjWork<T> Wk) {
+  constexpr int NT = 256;
+  constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  __shared__ T sP[W2 * H2];
+  __shared__ T sPx[W1 * H1], sPy[W1 * H1], sMu[W1 * H1], sRho[W1 * H1], sUx[W1 * H1],
+      sUy[W1 * H1];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
+  load_window<T, T, NT>(sUx, W1, H1, ukx, x0 - 1, y0 - 1, P, true);
+  load_window<T, T, NT>(sUy, W1, H1, uky, x0 - 1, y0 - 1, P, true);
+  __syncthreads();
+  const Tile<T> tP{sP, W2, 2};
+  derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
+  __syncthreads();
+  const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
+      tUx{sUx, W1, 1}, tUy{sUy, W1, 1};
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int ly = idx / TX, lx = idx % TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) continue;
+    const long long id = (long long)y * P.nx + x;
+    T vbx, vby;
+    if (FIRST) {
+      vbx = Wk.ukx_b[id];
+      vby = Wk.uky_b[id];
+      Wk.jx_b[id] = vbx;
+      Wk.jy_b[id] = vby;
+    } else {
+      vbx = fold<T, 1>(P, x, y, -1, -1,
+                       DivT<T>{zread(du_sel(Wk, src, 0), P), zread(du_sel(Wk, src, 1), P)});
+      vby = fold<T, 1>(P, x, y, -1, -1,
+                       DivT<T>{zread(du_sel(Wk, src, 2), P), zread(du_sel(Wk, src, 3), P)});
+      Wk.jx_b[id] = Wk.jx_b[id] + vbx;
+      Wk.jy_b[id] = Wk.jy_b[id] + vby;
+    }
+    const T p = praw[id];
+    ForceFwd<T> ff;
+    force_fwd<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, lx, ly, P, ff);
+    const T Fbx = vbx / (T(2) * ff.rho), Fby = vby / (T(2) * ff.rho);
+    const T rhob = -((Fbx * ff.Fx + Fby * ff.Fy) / ff.rho);
+    ForceAdj<T> fa;
+    force_adj<T>(ff, p, Fbx, Fby, P, fa);
+    Wk.praw_b[id] = Wk.praw_b[id] + fa.p;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) du_sel(Wk, 1 - src, k)[id] = fa.du[k];
+    Wk.a_phi[id] = Wk.a_phi[id] + props_adj<T>(tP(lx, ly), ff.rho, ff.nu, fa.rho + rhob, fa.nu, P);
+    Wk.a_grx[id] = Wk.a_grx[id] + fa.grx;
+    Wk.a_gry[id] = Wk.a_gry[id] + fa.gry;
+    Wk.a_dmx[id] = Wk.a_dmx[id] + fa.dmx;
+    Wk.a_dmy[id] = Wk.a_dmy[id] + fa.dmy;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) Wk.a_Q[k][id] = Wk.a_Q[k][id] + fa.Q[k];
+    Wk.sig[id] = Wk.sig[id] + double(fa.kappa) * C.dkap;
+    Wk.dM[id] = Wk.dM[id] + double(fa.cJ) * C.dcJ;
+  }
+}
+
+// ------------------------------------- phi-side transposes (a3^T and a5^T)
+// A: mu_bar = a_mu + grad^T(a_dm); rho_bar = grad^T(a_gr); adjoints of the
+// grad phi products and from them of (d_x phi, d_y phi); the first sweep's
+// velocity adjoint (grad^T of du[src]) joins the state's u~ adjoint.
+template <typename T, bool COUPLED>
+__global__ __launch_bounds__(256) void k_adj_phi_a(KParams<T> P, AdjConst C,
+                                                   const T* __restrict__ phi, int src,
+                                                   T* __restrict__ Uox, T* __restrict__ Uoy,
+                                                   AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const ERead<T> ph = eread(phi, P, false);
+  T mub = Wk.a_mu[id];
+  if (COUPLED)
+    mub = mub + fold<T, 1>(P, x, y, 1, 1, DivT<T>{zread(Wk.a_dmx, P), zread(Wk.a_dmy, P)});
+  Wk.mu_b[id] = mub;
+  const T p0 = ph(x, y);
+  const T dmu_dc4b = (p0 * p0) * p0 - p0;
+  const T dmu_dkap = -iso_lap<T>(ph, x, y);
+  Wk.sig[id] = Wk.sig[id] + double(mub * dmu_dc4b) * C.dc4b + double(mub * dmu_dkap) * C.dkap;
+  if (!COUPLED) return;
+  Wk.rho_b[id] = fold<T, 1>(P, x, y, 1, 1, DivT<T>{zread(Wk.a_grx, P), zread(Wk.a_gry, P)});
+  const T qyy = fold<T, 1>(P, x, y, 1, 1, GradXT<T>{zread(Wk.a_Q[0], P)});
+  const T qxy = fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(Wk.a_Q[1], P), zread(Wk.a_Q[2], P)});
+  const T qxx = fold<T, 1>(P, x, y, 1, 1, GradYT<T>{zread(Wk.a_Q[3], P)});
+  T px, py;
+  iso_grad<T>(ph, x, y, px, py);
+  Wk.px_b[id] = (T(2) * px) * qxx + py * qxy;
+  Wk.py_b[id] = (T(2) * py) * qyy + px * qxy;
+  Uox[id] = Uox[id] + fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(du_sel(Wk, src, 0), P),
+                                                          zread(du_sel(Wk, src, 1), P)});
+  Uoy[id] = Uoy[id] + fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(du_sel(Wk, src, 2), P),
+                                                          zread(du_sel(Wk, src, 3), P)});
+}
+
+// B: phi_bar (adjoint of phi^{n+1}) = pointwise part + mu^T + rho^T + grad^T
+// of the (d_x phi, d_y phi) adjoints + the loss seed.
+template <typename T, bool COUPLED>
+__global__ __launch_bounds__(256) void k_adj_phi_b(KParams<T> P, const T* __restrict__ phi,
+                                                   const double* __restrict__ seed,
+                                                   AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T p0 = phi[id];
+  const T mub = Wk.mu_b[id];
+  T r = Wk.a_phi[id] + (P.c4b * ((T(3) * p0) * p0 - T(1))) * mub;
+  r = r - P.kappa * fold<T, 1>(P, x, y, 1, 1, LapT<T>{zread(Wk.mu_b, P)});
+  if (COUPLED) {
+    if (p0 >= T(-1) && p0 <= T(1)) r = r + Wk.rho_b[id] * ((P.rho1 - P.rho2) / T(2));
+    r = r + fold<T, 1>(P, x, y, 1, 1, GradXT<T>{zread(Wk.px_b, P)});
+    r = r + fold<T, 1>(P, x, y, 1, 1, GradYT<T>{zread(Wk.py_b, P)});
+  }
+  if (seed) r = r + T(seed[id]);
+  Wk.phi_b[id] = r;
+}
+
+// ------------------------------------------------------ a2^T: FD stage
+// For a stage L(phi_s) with adjoint input a = coef * src (the RK3 weight of
+// the stage output), (A) the pointwise reverse of J_d at every node, given
+// J_d_bar = d4^T a; (B) mu_bar = d4^T of the grad-mu adjoints; (C) phi_s_bar
+// and the RK3 combination.
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adj_fd_a(KParams<T> P, AdjConst C, int tiles_x,
+                                                  const T* __restrict__ in,
+                                                  const T* __restrict__ src, T coef,
+                                                  AdjWork<T> Wk) {
+  constexpr int NT = 256;
+  constexpr int W3 = TX + 6, H3 = TY + 6;   // phi_s, halo 3
+  constexpr int W2 = TX + 4, H2 = TY + 4;   // mu, halo 2
+  __shared__ T sP[W3 * H3];
+  __shared__ T sM[W2 * H2];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT>(sP, W3, H3, in, x0 - 3, y0 - 3, P, false);
+  __syncthreads();
+  const Tile<T> tP{sP, W3, 3}, tM{sM, W2, 2};
+  for (int idx = threadIdx.x; idx < W2 * H2; idx += NT) {
+    const int ly = idx / W2 - 2, lx = idx % W2 - 2;
+    sM[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
+  }
+  __syncthreads();
+  const ZRead<T> La = zread(src, P);
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int ly = idx / TX, lx = idx % TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) continue;
+    const long long id = (long long)y * P.nx + x;
+    const T Jbx = coef * fold<T, 2>(P, x, y, -1, 1, D4XT<T>{La});
+    const T Jby = coef * fold<T, 2>(P, x, y, 1, -1, D4YT<T>{La});
+    const T Gx = d4<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
+    const T Gy = d4<T>(tP(lx, ly - 2), tP(lx, ly - 1), tP(lx, ly + 1), tP(lx, ly + 2));
+    const T Mx = d4<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
+    const T My = d4<T>(tM(lx, ly - 2), tM(lx, ly - 1), tM(lx, ly + 1), tM(lx, ly + 2));
+    const T ph = tP(lx, ly);
+    const T mag = sqrt((Gx * Gx + Gy * Gy) + P.eps2);
+    const T nx = Gx / mag, ny = Gy / mag;
+    const T cW = (T(2) * (T(1) - ph * ph)) / P.W;
+    const T s = Mx * nx + My * ny;
+    // J_d = lambda (mag - cW) n + (-M s) n
+    const T Jpbx = P.lam * Jbx, Jpby = P.lam * Jby;
+    const T qn = Jbx * nx + Jby * ny;          // q_bar . n
+    const T negMb = s * qn;
+    const T sb = P.negM * qn;
+    const T mc = mag - cW;
+    const T nbx = (P.negM * s) * Jbx + mc * Jpbx + sb * Mx;
+    const T nby = (P.negM * s) * Jby + mc * Jpby + sb * My;
+    const T t = Jpbx * nx + Jpby * ny;
+    const T magb = t - (nbx * nx + nby * ny) / mag;
+    Wk.fd_gx[id] = nbx / mag + magb * nx;
+    Wk.fd_gy[id] = nby / mag + magb * ny;
+    Wk.fd_mx[id] = sb * nx;
+    Wk.fd_my[id] = sb * ny;
+    Wk.fd_loc[id] = (-t) * ((T(-4) * ph) / P.W);
+    Wk.dM[id] = Wk.dM[id] - double(negMb);
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_fd_b(KParams<T> P, AdjConst C, const T* __restrict__ in,
+                                                  AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T mub = fold<T, 2>(P, x, y, 1, 1, D4XT<T>{zread(Wk.fd_mx, P)}) +
+                fold<T, 2>(P, x, y, 1, 1, D4YT<T>{zread(Wk.fd_my, P)});
+  Wk.fd_mu[id] = mub;
+  const ERead<T> ph = eread(in, P, false);
+  const T p0 = ph(x, y);
+  const T dmu_dc4b = (p0 * p0) * p0 - p0;
+  const T dmu_dkap = -iso_lap<T>(ph, x, y);
+  Wk.sig[id] = Wk.sig[id] + double(mub * dmu_dc4b) * C.dc4b + double(mub * dmu_dkap) * C.dkap;
+}
+
+// STAGE 3: phi2_bar = a + DL^T a, a = (2/3) phi_bar
+// STAGE 2: phi1_bar = a + DL^T a, a = phi2_bar / 4
+// STAGE 1: phib_bar = phi_bar/3 + (3/4) phi2_bar + phi1_bar + DL^T phi1_bar
+template <typename T, int STAGE>
+__global__ __launch_bounds__(256) void k_adj_fd_c(KParams<T> P, const T* __restrict__ in,
+                                                  AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T p0 = in[id];
+  T dl = Wk.fd_loc[id] + fold<T, 2>(P, x, y, 1, 1, D4XT<T>{zread(Wk.fd_gx, P)});
+  dl = dl + fold<T, 2>(P, x, y, 1, 1, D4YT<T>{zread(Wk.fd_gy, P)});
+  dl = dl + (P.c4b * ((T(3) * p0) * p0 - T(1))) * Wk.fd_mu[id];
+  dl = dl - P.kappa * fold<T, 1>(P, x, y, 1, 1, LapT<T>{zread(Wk.fd_mu, P)});
+  if (STAGE == 3) {
+    Wk.phi2_b[id] = (T(2) * Wk.phi_b[id]) / T(3) + dl;
+  } else if (STAGE == 2) {
+    Wk.phi1_b[id] = Wk.phi2_b[id] * T(0.25) + dl;
+  } else {
+    Wk.phib_b[id] = ((Wk.phi_b[id] / T(3) + Wk.phi2_b[id] * T(0.75)) + Wk.phi1_b[id]) + dl;
+  }
+}
+
+// ------------------------------------------- a1^T: gather and streaming
+// phi_bar = sum f_i, p = sum g_i / 3, j = sum g_i c_i reversed, added to the
+// canonical slot each pre-collision population streamed from.
+template <typename T, bool COUPLED>
+__global__ __launch_bounds__(256) void k_adj_gather(KParams<T> P, const T* __restrict__ phib_b,
+                                                    T* __restrict__ Afo, T* __restrict__ Ago,
+                                                    AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T pb = phib_b[id];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const long long s = src_slot(P, i, x, y);
+    Afo[s] = Afo[s] + pb;
+  }
+  if (!COUPLED) return;
+  const T q = Wk.praw_b[id] / T(3), jx = Wk.jx_b[id], jy = Wk.jy_b[id];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const long long s = src_slot(P, i, x, y);
+    Ago[s] = Ago[s] + (q + cdot(i, jx, jy));
+  }
+}
+
+// --------------------------------------------------- initial state^T
+// f* = f^eq(phi0, mu(phi0), u0): the pointwise reverse (phi, mu, eta), then
+// phi0_bar with the transposed Laplacian of mu_bar.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_init_a(KParams<T> P, AdjConst C,
+                                                    const double* __restrict__ phi0,
+                                                    const double* __restrict__ ux0,
+                                                    const double* __restrict__ uy0,
+                                                    const T* __restrict__ Af, AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  struct G {
+    const double* a;
+    const KParams<T>* P;
+    __device__ double operator()(int xx, int yy) const {
+      int flip = 0;
+      const int i = map_idx(xx, P->nx, P->wx, flip);
+      const int j = map_idx(yy, P->ny, P->wy, flip);
+      return a[(long long)j * P->nx + i];
+    }
+  } g{phi0, &P};
+  const T ph = T(phi0[id]);
+  const T mu = T(chem_pot<double>(g, x, y, C.c4b, C.kappa));
+  const T u_x = ux0 ? T(ux0[id]) : T(0), u_y = uy0 ? T(uy0[id]) : T(0);
+  T fb[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) fb[i] = Af[i * P.ps + id];
+  T phb = T(0), mub = T(0), ubx = T(0), uby = T(0), etab = T(0);
+  f_eq_adj<T>(ph, mu, u_x, u_y, P.eta, fb, phb, mub, ubx, uby, etab);
+  Wk.fd_loc[id] = phb;
+  Wk.fd_mu[id] = mub;
+  const double p0 = phi0[id];
+  const double dmu_dc4b = (p0 * p0) * p0 - p0;
+  const double dmu_dkap = -iso_lap<double>(g, x, y);
+  Wk.sig[id] = Wk.sig[id] + double(mub) * dmu_dc4b * C.dc4b + double(mub) * dmu_dkap * C.dkap;
+  Wk.dM[id] = Wk.dM[id] + double(etab) * C.deta;
+}
+
+// (add: dL/dphi of a zero-step run, whose phi is phi0 itself; may be NULL)
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_init_b(KParams<T> P, const double* __restrict__ phi0,
+                                                    const double* __restrict__ add,
+                                                    double* __restrict__ out, AdjWork<T> Wk) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  const T p0 = T(phi0[id]);
+  T r = Wk.fd_loc[id] + (P.c4b * ((T(3) * p0) * p0 - T(1))) * Wk.fd_mu[id];
+  r = r - P.kappa * fold<T, 1>(P, x, y, 1, 1, LapT<T>{zread(Wk.fd_mu, P)});
+  out[id] = add ? double(r) + add[id] : double(r);
+}
+
+// deterministic sum of a float64 plane: per-block partials in a fixed tree
+// order, then one block over the partials (one copy per translation unit)
+namespace {
+__global__ __launch_bounds__(256) void k_sum1(const double* __restrict__ a, long long n,
+                                              double* __restrict__ part) {
+  __shared__ double s[256];
+  double acc = 0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (long long)gridDim.x * 256)
+    acc += a[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ part, int nb,
+                                              double* __restrict__ out) {
+  __shared__ double s[256];
+  double acc = 0;
+  for (int b = threadIdx.x; b < nb; b += 256) acc += part[b];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+}  // namespace
+
+// gather m7, m8 of the pre-collision g (the stress moments the g-collision's
+// rate derivative needs), written while a step is recomputed for the adjoint
+template <typename T, int PAR>
+__global__ __launch_bounds__(256) void k_rec_m78(KParams<T> P, const T* __restrict__ Ag,
+                                                 T* __restrict__ m7, T* __restrict__ m8) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  int rd[9];
+  slots<PAR>(P, x, y, rd);
+  T g[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) g[i] = Ag[rd[i]];
+  m7[id] = ((g[1] - g[2]) + g[3]) - g[4];
+  m8[id] = ((g[5] - g[6]) + g[7]) - g[8];
+}
+
+}  // namespace lbm2p

@@ -1,0 +1,366 @@
+// Host orchestration of the adjoint: the recorded forward run with its
+// checkpoints, and the reverse sweep segment by segment (recompute the
+// segment's steps into per-step slots, then reverse them last to first).
+// Included once per precision translation unit, after lbm2p_impl.h.
+#pragma once
+
+#include "lbm2p_impl.h"
+
+namespace lbm2p {
+namespace {
+
+// planes of one recorded step
+template <typename T>
+struct Slot {
+  T *phibar, *phi1, *phi2, *phi, *praw, *pt, *utx, *uty, *m7, *m8;
+  T* u[8][2];  // u^1 .. u^{K-1}
+};
+
+template <typename T>
+struct AdjPtrs {
+  AdjLayout L;
+  char* base;
+  T* ckpt(int i) const { return (T*)(base + L.ckpt + (size_t)i * L.cpp * L.plane); }
+  T* plane(size_t off, int i) const { return (T*)(base + off + (size_t)i * L.plane); }
+  Slot<T> slot(int j, const lbm2p_params& p) const {
+    Slot<T> s{};
+    T* b = (T*)(base + L.slot + (size_t)j * L.slp * L.plane);
+    const long long ps = (long long)(L.plane / sizeof(T));
+    int k = 0;
+    s.phibar = b + (k++) * ps;
+    s.phi1 = b + (k++) * ps;
+    s.phi2 = b + (k++) * ps;
+    s.phi = b + (k++) * ps;
+    if (p.coupled) {
+      s.praw = b + (k++) * ps;
+      for (int i = 1; i < p.K; ++i) {
+        s.u[i][0] = b + (k++) * ps;
+        s.u[i][1] = b + (k++) * ps;
+      }
+      s.pt = b + (k++) * ps;
+      s.utx = b + (k++) * ps;
+      s.uty = b + (k++) * ps;
+      s.m7 = b + (k++) * ps;
+      s.m8 = b + (k++) * ps;
+    }
+    return s;
+  }
+  // adjoint state copy a: f (9 planes), g (9, coupled), u (2)
+  T* astate(int a) const { return (T*)(base + L.astate + (size_t)a * (L.sp + 2) * L.plane); }
+  double* dbl() const { return (double*)(base + L.dbl); }
+};
+
+template <typename T>
+AdjWork<T> adj_work(const AdjPtrs<T>& A) {
+  AdjWork<T> w;
+  int k = 0;
+  auto nx = [&]() { return A.plane(A.L.work, k++); };
+  w.lp_p = nx(); w.lp_ux = nx(); w.lp_uy = nx(); w.dp_x = nx(); w.dp_y = nx();
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 4; ++b) w.du[a][b] = nx();
+  w.a_phi = nx(); w.a_mu = nx(); w.a_grx = nx(); w.a_gry = nx(); w.a_dmx = nx(); w.a_dmy = nx();
+  for (int b = 0; b < 4; ++b) w.a_Q[b] = nx();
+  w.mu_b = nx(); w.rho_b = nx(); w.px_b = nx(); w.py_b = nx();
+  w.pt_b = nx(); w.utx_b = nx(); w.uty_b = nx(); w.ukx_b = nx(); w.uky_b = nx();
+  w.praw_b = nx(); w.jx_b = nx(); w.jy_b = nx();
+  w.phi_b = nx(); w.phi2_b = nx(); w.phi1_b = nx(); w.phib_b = nx();
+  w.fd_gx = nx(); w.fd_gy = nx(); w.fd_mx = nx(); w.fd_my = nx(); w.fd_loc = nx(); w.fd_mu = nx();
+  w.sig = A.dbl();
+  w.dM = A.dbl() + (size_t)(A.L.plane / sizeof(T));
+  return w;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* a, T v, long long n) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id < n) a[id] = v;
+}
+
+inline AdjConst adj_const(const lbm2p_ctx* c) {
+  const lbm2p_params& p = c->p;
+  AdjConst C;
+  C.dc4b = 3.0 / p.W;
+  C.dkap = 3.0 * p.W / 8.0;
+  C.deta = 3.0 / (p.tau_f - 0.5);
+  C.dcJ = (p.rho1 - p.rho2) / 2.0;
+  C.c4b = c->c4b;
+  C.kappa = c->kappa;
+  return C;
+}
+
+// checkpoint i <- current state (populations in the AA layout, u~, phi, p~)
+template <typename T>
+void save_ckpt(lbm2p_ctx* c, const AdjPtrs<T>& A, int i) {
+  const long long ps = c->ps;
+  T* d = A.ckpt(i);
+  const int nd = c->p.coupled ? 2 : 1;
+  k_copy<T><<<blocks1d(9 * ps), 256, 0, c->stream>>>((const T*)c->Af, d, 9 * ps);
+  if (nd == 2) k_copy<T><<<blocks1d(9 * ps), 256, 0, c->stream>>>((const T*)c->Ag, d + 9 * ps, 9 * ps);
+  T* u = d + 9 * nd * ps;
+  const int ui = c->p.coupled ? c->uo : 0;
+  k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>((const T*)c->U[ui][0], u, ps);
+  k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>((const T*)c->U[ui][1], u + ps, ps);
+  k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>((const T*)c->phi, u + 2 * ps, ps);
+  if (c->p.coupled) k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>((const T*)c->pt, u + 3 * ps, ps);
+}
+
+// current state <- checkpoint i (u~ into U[0]; the context's own planes)
+template <typename T>
+void load_ckpt(lbm2p_ctx* c, const AdjPtrs<T>& A, int i, int parity, bool fields) {
+  const long long ps = c->ps;
+  const T* d = A.ckpt(i);
+  const int nd = c->p.coupled ? 2 : 1;
+  k_copy<T><<<blocks1d(9 * ps), 256, 0, c->stream>>>(d, (T*)c->Af, 9 * ps);
+  if (nd == 2) k_copy<T><<<blocks1d(9 * ps), 256, 0, c->stream>>>(d + 9 * ps, (T*)c->Ag, 9 * ps);
+  const T* u = d + 9 * nd * ps;
+  if (c->p.coupled) {
+    k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>(u, (T*)c->U[0][0], ps);
+    k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>(u + ps, (T*)c->U[0][1], ps);
+  }
+  if (fields) {
+    k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>(u + 2 * ps, (T*)c->phi, ps);
+    if (c->p.coupled) k_copy<T><<<blocks1d(ps), 256, 0, c->stream>>>(u + 3 * ps, (T*)c->pt, ps);
+  }
+  c->parity = parity;
+  c->uo = 0;
+}
+
+template <typename T>
+int record_impl(lbm2p_ctx* c, int nsteps, int k) {
+  AdjPtrs<T> A{adj_layout(c->p, c->ps, c->n, c->esz, nsteps, k), c->adj_ws};
+  c->adj_ready = 0;
+  c->adj_nsteps = nsteps;
+  c->adj_k = k;
+  c->adj_from_init = c->from_init && c->steps == 0;
+  c->adj_parity0 = c->parity;
+  save_ckpt<T>(c, A, 0);
+  for (int s = 0; s < nsteps; ++s) {
+    const int e = step_impl<T>(c, 1);
+    if (e) return e;
+    if ((s + 1) % k == 0 && s + 1 < nsteps) save_ckpt<T>(c, A, (s + 1) / k);
+  }
+  save_ckpt<T>(c, A, A.L.nseg);
+  c->adj_steps_end = c->steps;
+  c->adj_ready = 1;
+  return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
+}
+
+// one reverse step: adjoint state in (ai) -> out (1 - ai)
+template <typename T>
+void adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, const Slot<T>& sl,
+              const T* uox, const T* uoy, const double* seed, int ai) {
+  const lbm2p_params& p = c->p;
+  const KParams<T> K = kparams<T>(c);
+  const AdjConst C = adj_const(c);
+  hipStream_t st = c->stream;
+  const long long n = c->n, ps = c->ps;
+  const unsigned nb = blocks1d(n);
+  T* Ai = A.astate(ai);
+  T* Ao = A.astate(1 - ai);
+  const int sp = A.L.sp;
+  const T* Afi = Ai;
+  const T* Agi = p.coupled ? Ai + 9 * ps : nullptr;
+  const T* Uix = Ai + sp * ps;
+  const T* Uiy = Uix + ps;
+  T* Afo = Ao;
+  T* Ago = p.coupled ? Ao + 9 * ps : nullptr;
+  T* Uox = Ao + sp * ps;
+  T* Uoy = Uox + ps;
+  const Tiles<COL_TX, COL_TY> tc(p);
+  if (p.coupled) {
+    k_adj_collide<T, true, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
+        K, C, tc.tx, sl.phi, sl.pt, sl.utx, sl.uty, uox, uoy, sl.m7, sl.m8, Afi, Agi, Afo, Ago, Uox,
+        Uoy, Wk);
+    k_adj_collide_t<T><<<nb, 256, 0, st>>>(K, Uix, Uiy, Wk);
+    switch (p.filter_n ? c->fn : 0) {
+      case 0: k_adj_filter<T, 0><<<nb, 256, 0, st>>>(K, Wk); break;
+      case 2: k_adj_filter<T, 2><<<nb, 256, 0, st>>>(K, Wk); break;
+      case 3: k_adj_filter<T, 3><<<nb, 256, 0, st>>>(K, Wk); break;
+      case 4: k_adj_filter<T, 4><<<nb, 256, 0, st>>>(K, Wk); break;
+      default: k_adj_filter<T, 5><<<nb, 256, 0, st>>>(K, Wk); break;
+    }
+    // velocity sweeps last to first; sweep k reads u^k (u^0 = u~^n)
+    int cur = 0;
+    const Tiles<VEL_TX, VEL_TY> tv(p);
+    for (int k = p.K - 1; k >= 0; --k) {
+      const T* ux = k == 0 ? uox : sl.u[k][0];
+      const T* uy = k == 0 ? uoy : sl.u[k][1];
+      if (k == p.K - 1) {
+        k_adj_vel<T, true, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(K, C, tv.tx, sl.phi, sl.praw,
+                                                                      ux, uy, 1, Wk);
+        cur = 0;
+      } else {
+        k_adj_vel<T, false, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(K, C, tv.tx, sl.phi,
+                                                                       sl.praw, ux, uy, cur, Wk);
+        cur = 1 - cur;
+      }
+    }
+    k_adj_phi_a<T, true><<<nb, 256, 0, st>>>(K, C, sl.phi, cur, Uox, Uoy, Wk);
+    k_adj_phi_b<T, true><<<nb, 256, 0, st>>>(K, sl.phi, seed, Wk);
+  } else {
+    const T* ux = (const T*)c->U[0][0];
+    const T* uy = (const T*)c->U[0][1];
+    k_adj_collide<T, false, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
+        K, C, tc.tx, sl.phi, nullptr, ux, uy, ux, uy, nullptr, nullptr, Afi, nullptr, Afo, nullptr,
+        nullptr, nullptr, Wk);
+    k_adj_phi_a<T, false><<<nb, 256, 0, st>>>(K, C, sl.phi, 0, nullptr, nullptr, Wk);
+    k_adj_phi_b<T, false><<<nb, 256, 0, st>>>(K, sl.phi, seed, Wk);
+  }
+  const T* phib = Wk.phi_b;
+  if (!p.original_ch) {
+    const Tiles<FD_TX, FD_TY> tf(p);
+    const T* in[3] = {sl.phi2, sl.phi1, sl.phibar};
+    const T* src[3] = {Wk.phi_b, Wk.phi2_b, Wk.phi1_b};
+    const T coef[3] = {T(2.0 / 3.0), T(0.25), T(1)};
+    for (int s = 0; s < 3; ++s) {
+      k_adj_fd_a<T, FD_TX, FD_TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, in[s], src[s], coef[s], Wk);
+      k_adj_fd_b<T><<<nb, 256, 0, st>>>(K, C, in[s], Wk);
+      if (s == 0) k_adj_fd_c<T, 3><<<nb, 256, 0, st>>>(K, in[s], Wk);
+      else if (s == 1) k_adj_fd_c<T, 2><<<nb, 256, 0, st>>>(K, in[s], Wk);
+      else k_adj_fd_c<T, 1><<<nb, 256, 0, st>>>(K, in[s], Wk);
+    }
+    phib = Wk.phib_b;
+  }
+  if (p.coupled)
+    k_adj_gather<T, true><<<nb, 256, 0, st>>>(K, phib, Afo, Ago, Wk);
+  else
+    k_adj_gather<T, false><<<nb, 256, 0, st>>>(K, phib, Afo, nullptr, Wk);
+}
+
+template <typename T>
+int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
+  const lbm2p_params& p = c->p;
+  const int nsteps = c->adj_nsteps, k = c->adj_k;
+  AdjPtrs<T> A{adj_layout(p, c->ps, c->n, c->esz, nsteps, k), c->adj_ws};
+  const AdjWork<T> Wk = adj_work<T>(A);
+  const long long n = c->n, ps = c->ps;
+  hipStream_t st = c->stream;
+  const int sp = A.L.sp;
+  // seeds into adjoint state 0; zero the parameter partials
+  T* A0 = A.astate(0);
+  k_fill<T><<<blocks1d((sp + 2) * ps), 256, 0, st>>>(A0, T(0), (sp + 2) * ps);
+  k_fill<double><<<blocks1d(2 * ps), 256, 0, st>>>(A.dbl(), 0.0, 2 * ps);
+  for (int i = 0; i < 9; ++i) {
+    if (io->dL_df)
+      k_from_f64<T><<<blocks1d(n), 256, 0, st>>>(io->dL_df + i * n, A0 + i * ps, n);
+    if (p.coupled && io->dL_dg)
+      k_from_f64<T><<<blocks1d(n), 256, 0, st>>>(io->dL_dg + i * n, A0 + (9 + i) * ps, n);
+  }
+  if (p.coupled && io->dL_du)
+    for (int d = 0; d < 2; ++d)
+      k_from_f64<T><<<blocks1d(n), 256, 0, st>>>(io->dL_du + d * n, A0 + (sp + d) * ps, n);
+  // the context's own planes, rebound per recomputed step
+  void* own_phibar = c->phibar;
+  void* own_phi1 = c->phi1;
+  void* own_phi2 = c->phi2;
+  void* own_phi = c->phi;
+  void* own_praw = c->praw;
+  void* own_pt = c->pt;
+  void* own_U[2][2] = {{c->U[0][0], c->U[0][1]}, {c->U[1][0], c->U[1][1]}};
+  int ai = 0;
+  for (int seg = A.L.nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * k;
+    const int len = std::min(k, nsteps - s0);
+    c->U[0][0] = own_U[0][0];
+    c->U[0][1] = own_U[0][1];
+    c->U[1][0] = own_U[1][0];
+    c->U[1][1] = own_U[1][1];
+    load_ckpt<T>(c, A, seg, c->adj_parity0 ^ (s0 & 1), false);
+    c->rec = 1;
+    for (int j = 0; j < len; ++j) {
+      const Slot<T> sl = A.slot(j, p);
+      c->phibar = sl.phibar;
+      c->phi1 = sl.phi1;
+      c->phi2 = sl.phi2;
+      c->phi = sl.phi;
+      if (p.coupled) {
+        c->praw = sl.praw;
+        c->pt = sl.pt;
+        c->U[1 - c->uo][0] = sl.utx;
+        c->U[1 - c->uo][1] = sl.uty;
+        for (int i = 1; i < p.K; ++i) {
+          c->rec_uk[i - 1][0] = sl.u[i][0];
+          c->rec_uk[i - 1][1] = sl.u[i][1];
+        }
+        c->rec_uk[p.K - 1][0] = c->uk[0][0];
+        c->rec_uk[p.K - 1][1] = c->uk[0][1];
+        c->rec_m7 = sl.m7;
+        c->rec_m8 = sl.m8;
+      }
+      const int e = step_impl<T>(c, 1);
+      if (e) {
+        c->rec = 0;
+        return e;
+      }
+    }
+    c->rec = 0;
+    const T* cku = A.ckpt(seg) + (size_t)9 * (p.coupled ? 2 : 1) * ps;
+    for (int j = len - 1; j >= 0; --j) {
+      const Slot<T> sl = A.slot(j, p);
+      const T* uox = nullptr;
+      const T* uoy = nullptr;
+      if (p.coupled) {
+        if (j == 0) {
+          uox = cku;
+          uoy = cku + ps;
+        } else {
+          const Slot<T> pr = A.slot(j - 1, p);
+          uox = pr.utx;
+          uoy = pr.uty;
+        }
+      }
+      const double* seed = (s0 + j == nsteps - 1) ? io->dL_dphi : nullptr;
+      adj_step<T>(c, A, Wk, sl, uox, uoy, seed, ai);
+      ai = 1 - ai;
+    }
+  }
+  // back to the context's own planes and the recorded final state
+  c->phibar = own_phibar;
+  c->phi1 = own_phi1;
+  c->phi2 = own_phi2;
+  c->phi = own_phi;
+  c->praw = own_praw;
+  c->pt = own_pt;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) c->U[a][b] = own_U[a][b];
+  load_ckpt<T>(c, A, A.L.nseg, c->adj_parity0 ^ (nsteps & 1), true);
+  c->steps = c->adj_steps_end;
+  // outputs
+  const KParams<T> K = kparams<T>(c);
+  T* Af = A.astate(ai);
+  for (int i = 0; i < 9; ++i) {
+    if (io->dL_df0) k_to_f64<T><<<blocks1d(n), 256, 0, st>>>(Af + i * ps, io->dL_df0 + i * n, n);
+    if (p.coupled && io->dL_dg0)
+      k_to_f64<T><<<blocks1d(n), 256, 0, st>>>(Af + (9 + i) * ps, io->dL_dg0 + i * n, n);
+  }
+  if (io->dL_du0) {
+    for (int d = 0; d < 2; ++d) {
+      if (p.coupled)
+        k_to_f64<T><<<blocks1d(n), 256, 0, st>>>(Af + (sp + d) * ps, io->dL_du0 + d * n, n);
+      else
+        k_fill<double><<<blocks1d(n), 256, 0, st>>>(io->dL_du0 + d * n, 0.0, n);
+    }
+  }
+  if (io->dL_dphi0) {
+    k_adj_init_a<T><<<blocks1d(n), 256, 0, st>>>(K, adj_const(c), io->phi0, io->ux0, io->uy0, Af,
+                                                 Wk);
+    k_adj_init_b<T><<<blocks1d(n), 256, 0, st>>>(K, io->phi0, nsteps == 0 ? io->dL_dphi : nullptr,
+                                                 io->dL_dphi0, Wk);
+  }
+  double* part = A.dbl() + 2 * ps;
+  double* res = part + 1024;
+  k_sum1<<<1024, 256, 0, st>>>(Wk.sig, n, part);
+  k_sum2<<<1, 256, 0, st>>>(part, 1024, res);
+  k_sum1<<<1024, 256, 0, st>>>(Wk.dM, n, part);
+  k_sum2<<<1, 256, 0, st>>>(part, 1024, res + 1);
+  double h[2];
+  if (hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return LBM2P_EHIP;
+  if (hipStreamSynchronize(st) != hipSuccess) return LBM2P_EHIP;
+  io->dL_dsigma = h[0];
+  io->dL_dM = h[1];
+  return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
+}
+
+}  // namespace
+}  // namespace lbm2p

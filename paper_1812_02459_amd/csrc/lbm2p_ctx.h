@@ -44,7 +44,55 @@ struct lbm2p_ctx {
   int prof_pass;
   std::vector<hipEvent_t> ev0, ev1;
   size_t prof_n;
+  // adjoint: record mode of the step (every velocity sweep to its own plane,
+  // the stress moments m7, m8 of the pre-collision g) and the recorded run
+  int rec;
+  void* rec_uk[8][2];
+  void *rec_m7, *rec_m8;
+  int from_init;          // the state is the one lbm2p_init_fields made
+  char* adj_ws;
+  size_t adj_bytes;
+  int adj_nsteps, adj_k, adj_from_init, adj_parity0, adj_ready;
+  long long adj_steps_end;
 };
+
+namespace lbm2p {
+
+// Layout of the adjoint workspace (byte offsets, each region 256-aligned):
+//   checkpoints: ncp = segments + 1 states (populations, u~, and phi, p~ for
+//                the final one), in the context's precision and AA layout;
+//   slots:       k per-step records of a segment (phi_bar, phi^(1), phi^(2),
+//                phi, then coupled: p, u^1..u^{K-1}, p~, u~, m7, m8);
+//   adjoint state: two canonical copies of (f*, g*, u~) adjoints;
+//   work:        the reverse step's planes;
+//   float64:     per-node dL/dsigma, dL/dM partials and the reduction scratch.
+struct AdjLayout {
+  int nseg, ncp, sp, cpp, slp, wp;
+  size_t plane, ckpt, slot, astate, work, dbl, total;
+};
+
+inline AdjLayout adj_layout(const lbm2p_params& p, long long ps, long long n, size_t esz,
+                            int nsteps, int k) {
+  auto al = [](size_t v) { return (v + 255) / 256 * 256; };
+  AdjLayout L;
+  L.nseg = nsteps > 0 ? (nsteps + k - 1) / k : 0;
+  L.ncp = L.nseg + 1;
+  L.sp = p.coupled ? 18 : 9;
+  L.cpp = L.sp + 4;
+  L.slp = p.coupled ? 10 + 2 * (p.K - 1) : 4;
+  L.wp = 45;
+  L.plane = (size_t)ps * esz;
+  const int kk = nsteps < k ? (nsteps > 0 ? nsteps : 1) : k;
+  L.ckpt = 0;
+  L.slot = al(L.ckpt + (size_t)L.ncp * L.cpp * L.plane);
+  L.astate = al(L.slot + (size_t)kk * L.slp * L.plane);
+  L.work = al(L.astate + (size_t)2 * (L.sp + 2) * L.plane);
+  L.dbl = al(L.work + (size_t)L.wp * L.plane);
+  L.total = al(L.dbl + ((size_t)2 * ps + 1024 + 64) * sizeof(double));
+  return L;
+}
+
+}  // namespace lbm2p
 
 
 namespace lbm2p {
@@ -59,7 +107,9 @@ namespace lbm2p {
   int moments_##SUF(lbm2p_ctx*, double*, double*, double*, double*, double*);    \
   int volume_##SUF(lbm2p_ctx*, double*);                                          \
   int state_##SUF(lbm2p_ctx*, double*, double*, double*, int);                    \
-  int to_f64_##SUF(lbm2p_ctx*, const void*, double*);
+  int to_f64_##SUF(lbm2p_ctx*, const void*, double*);                             \
+  int record_##SUF(lbm2p_ctx*, int, int);                                         \
+  int adjoint_##SUF(lbm2p_ctx*, lbm2p_adjoint_io*);
 LBM2P_DECLARE(f64)
 LBM2P_DECLARE(f32)
 #undef LBM2P_DECLARE

@@ -1,7 +1,7 @@
 // float instantiation of the lattice update, compiled with contraction into fused multiply-adds and fast
 // single-precision division (the FP32 mode is held to error bounds, not to
 // bitwise agreement).
-#include "lbm2p_impl.h"
+#include "lbm2p_adjoint_impl.h"
 
 namespace lbm2p {
 
@@ -21,5 +21,8 @@ int to_f64_f32(lbm2p_ctx* c, const void* src, double* dst) {
   to_f64<float>(c, src, dst);
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
+
+int record_f32(lbm2p_ctx* c, int nsteps, int k) { return record_impl<float>(c, nsteps, k); }
+int adjoint_f32(lbm2p_ctx* c, lbm2p_adjoint_io* io) { return adjoint_impl<float>(c, io); }
 
 }  // namespace lbm2p

@@ -1,6 +1,6 @@
 // double instantiation of the lattice update, compiled without floating-point contraction: every expression rounds
 // as written, like the CPU oracle.
-#include "lbm2p_impl.h"
+#include "lbm2p_adjoint_impl.h"
 
 namespace lbm2p {
 
@@ -20,5 +20,8 @@ int to_f64_f64(lbm2p_ctx* c, const void* src, double* dst) {
   to_f64<double>(c, src, dst);
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
+
+int record_f64(lbm2p_ctx* c, int nsteps, int k) { return record_impl<double>(c, nsteps, k); }
+int adjoint_f64(lbm2p_ctx* c, lbm2p_adjoint_io* io) { return adjoint_impl<double>(c, io); }
 
 }  // namespace lbm2p

@@ -9,6 +9,7 @@
 #include "lbm2p_ctx.h"
 #include "lbm2p_kernels.h"
 #include "lbm2p_compact.h"
+#include "lbm2p_adjoint.h"
 
 namespace lbm2p {
 namespace {
@@ -328,6 +329,12 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
                                                               nullptr);
       }
     }
+    if (c->rec && p.coupled) {
+      if (par == 0)
+        k_rec_m78<T, 0><<<blocks1d(n), 256, 0, st>>>(K, Ag, (T*)c->rec_m7, (T*)c->rec_m8);
+      else
+        k_rec_m78<T, 1><<<blocks1d(n), 256, 0, st>>>(K, Ag, (T*)c->rec_m7, (T*)c->rec_m8);
+    }
     if (p.original_ch) {
       k_copy<T><<<blocks1d(n), 256, 0, st>>>(phibar, phi, n);
     } else {
@@ -355,13 +362,14 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       const Tiles<VEL_TX, VEL_TY> tv(p);
       int done = 0, launch = 0;
       while (done < p.K) {
-        // two sweeps per launch, one for an odd remainder
-        T* ox = (T*)c->uk[launch & 1][0];
-        T* oy = (T*)c->uk[launch & 1][1];
+        // two sweeps per launch, one for an odd remainder; when recording for
+        // the adjoint, one sweep per launch, each iterate to its own plane
+        T* ox = (T*)(c->rec ? c->rec_uk[launch][0] : c->uk[launch & 1][0]);
+        T* oy = (T*)(c->rec ? c->rec_uk[launch][1] : c->uk[launch & 1][1]);
         ProfScope ps(c, PASS_VEL);
         // (FP64: one sweep per launch -- the two-sweep kernel's LDS footprint
         // costs more occupancy than its saved traffic is worth in double)
-        if (sizeof(T) == 4 && p.K - done >= 2) {
+        if (sizeof(T) == 4 && p.K - done >= 2 && !c->rec) {
           k_vel<T, 2, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(
               K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
           done += 2;
@@ -426,6 +434,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
     }
     c->parity ^= 1;
     c->steps++;
+    c->from_init = 0;
   }
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
@@ -451,6 +460,8 @@ int init_impl(lbm2p_ctx* c, const double* phi0, const double* ux0, const double*
   c->parity = 0;
   c->steps = 0;
   c->inited = 1;
+  c->from_init = 1;
+  c->adj_ready = 0;
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
 
@@ -498,6 +509,10 @@ int volume_impl(lbm2p_ctx* c, double out[6]) {
 template <typename T>
 int state_impl(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
   const KParams<T> K = kparams<T>(c);
+  if (set) {
+    c->from_init = 0;
+    c->adj_ready = 0;
+  }
   if (f) k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Af, f, c->parity, set);
   if (g && c->p.coupled)
     k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Ag, g, c->parity, set);

@@ -174,19 +174,30 @@ def bubble_ensemble(n=4096, nb=200, seed=0, steps=2000, rmin=10.0, rmax=60.0,
                     dict(nb=nb, bubbles=bl, g=g))
 
 
-def rising_bubble(nx=256, ny=1024, R=32.0, xc=128.0, yc=128.0, sigma=1e-3, Eo=10.0,
-                  Re=35.0, steps=4000, sigma_ref=1e-3):
-    """Rising bubble in a closed box (walls on all sides), Sec. 4.5 set-up;
-    g and viscosities fixed from Eo and Re at sigma_ref."""
+def rising_bubble(nx=256, ny=1024, R=32.0, xc=128.0, yc=128.0, sigma=None, Eo=10.0,
+                  Re=35.0, steps=4000, U_g=None, sigma_ref=1e-3):
+    """Gas bubble rising in liquid in a closed box (walls on all sides), the
+    Sec. 4.5 set-up: density ratio 1000, viscosity ratio 100, Eo and Re at the
+    initial radius.  Without U_g, g follows from Eo at sigma_ref (g = 2.441e-6
+    for R = 32); with U_g = sqrt(2 g R) given, g = U_g^2/(2R) and
+    sigma_0 = 2 rho1 U_g^2 R / Eo.  g and the viscosities stay fixed when sigma
+    is varied (sigma = None: sigma_ref, or sigma_0 with U_g)."""
     rho1, rho2 = 1.0, 1e-3
-    g = Eo * sigma_ref / (4.0 * rho1 * R * R)
-    U_g = math.sqrt(2.0 * g * R)
+    if U_g is None:
+        g = Eo * sigma_ref / (4.0 * rho1 * R * R)
+        U_g = math.sqrt(2.0 * g * R)
+        sig0 = sigma_ref
+    else:
+        g = U_g * U_g / (2.0 * R)
+        sig0 = 2.0 * rho1 * U_g * U_g * R / Eo
+    sigma = sig0 if sigma is None else sigma
     mu1 = rho1 * U_g * 2.0 * R / Re
     phi = drop_field(nx, ny, xc, yc, R, 4.0, inside=-1.0, periodic=False)
     z = np.zeros_like(phi)
     prm = base_params(nx, ny, wall_x=True, wall_y=True, rho1=rho1, rho2=rho2,
                       mu1=mu1, mu2=mu1 / 100.0, sigma=sigma, gy=-g, rho_ref=0.0)
-    return Workload("rising", prm, phi, z, z.copy(), z.copy(), steps, dict(g=g))
+    return Workload("rising", prm, phi, z, z.copy(), z.copy(), steps,
+                    dict(g=g, U_g=U_g, sigma0=sig0, R=R))
 
 
 def random_smooth(nx, ny, seed, amp=1.0, modes=4):

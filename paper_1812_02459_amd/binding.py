@@ -9,6 +9,11 @@ import ctypes
 import os
 
 import numpy as np
+# torch ships its own HIP runtime under the same soname as the system one
+# (libamdhip64.so.7); whichever is loaded first serves the whole process.  Load
+# torch's before the library so that torch and the library share one runtime
+# (the library is handed torch's memory and streams).
+import torch  # noqa: F401
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblbm2p.so")

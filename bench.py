@@ -9,7 +9,9 @@ collide).  Inputs are resident in HBM before timing starts.
 
 Prints one JSON line: MLUPS of the FP32 step (the headline), the FP64 step,
 the roofline of the dominant kernel (the fused collide) from HIP events on the
-library's stream, and the CPU oracle's rate on a bounded sample.
+library's stream, the adjoint's cost against the forward step on the
+closed-box rising bubble (256 x 1024), and the CPU oracle's rate on a bounded
+sample.
 """
 
 import argparse
@@ -17,6 +19,8 @@ import json
 import os
 import sys
 import time
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
@@ -69,6 +73,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=1024, help="CPU sample window side")
     ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adj-steps", type=int, default=640, help="steps of the adjoint timing")
     return ap.parse_args()
 
 
@@ -114,6 +120,45 @@ def run_precision(wl, precision, steps, warmup):
     return res
 
 
+def adjoint_cost(precision, nsteps, k=64, warmup=64):
+    """Forward step time against the adjoint's time per step (segment recompute
+    plus reverse sweep, checkpoints every k steps) on the closed-box rising
+    bubble, 256 x 1024, R = 32, loss seed 2 (phi_T - phi*)/N."""
+    import torch
+    from paper_1812_02459_amd import inputs as I
+    from paper_1812_02459_amd.binding import Sim
+    wl = I.rising_bubble()
+    sim = Sim(wl.params, precision=precision)
+    sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(nsteps)
+    torch.cuda.synchronize()
+    t_fwd = (time.perf_counter() - t0) / nsteps
+    sim.close()
+    sim = Sim(wl.params, precision=precision)
+    sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.record(nsteps, k)
+    torch.cuda.synchronize()
+    t_rec = (time.perf_counter() - t0) / nsteps
+    phiT = sim.moments()["phi"]
+    seed = 2.0 * (phiT - torch.tanh(phiT)) / phiT.numel()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sim.adjoint(dL_dphi=seed, want_phi0=True)
+    torch.cuda.synchronize()
+    t_adj = (time.perf_counter() - t0) / nsteps
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return dict(fwd_us_per_step=round(t_fwd * 1e6, 2), record_us_per_step=round(t_rec * 1e6, 2),
+                adj_us_per_step=round(t_adj * 1e6, 2), ratio=round(t_adj / t_fwd, 3),
+                steps=nsteps, ckpt_every=k, finite=bool(np.isfinite(g["sigma"])))
+
+
 def copy_bandwidth():
     import torch
     n = 1 << 28  # 1 GiB of float32
@@ -138,7 +183,8 @@ def cpu_baseline(wl, side, steps):
     parameters (periodic window), timed on this host's cores."""
     import torch
     import oracle
-    torch.set_num_threads(os.cpu_count() or 1)
+    # the host's CPU share (OMP_NUM_THREADS where the job sets it), else every core
+    torch.set_num_threads(int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count() or 1))
     p = dict(wl.params)
     p["nx"] = p["ny"] = side
     prm = oracle.Params(**p)
@@ -175,6 +221,17 @@ def main():
         r64 = run_precision(wl, 0, args.steps, args.warmup)
         print(f"# fp64: {r64['mlups']:.0f} MLUPS, collide {r64['collide_ms']:.3f} ms "
               f"({r64['collide_gbps']:.0f} GB/s)", file=sys.stderr, flush=True)
+    adj = None
+    if not args.no_adjoint:
+        adj = {"workload": "closed-box rising bubble 256x1024, R=32, walls on all sides, "
+                           "rho1/rho2=1000, Eo=10, Re=35, U_g=2e-3; adjoint time = segment "
+                           "recompute + reverse sweep, per step",
+               "fp32": adjoint_cost(1, args.adj_steps)}
+        if not args.no_fp64:
+            adj["fp64"] = adjoint_cost(0, args.adj_steps)
+        print(f"# adjoint/forward: fp32 {adj['fp32']['ratio']:.2f}"
+              + (f", fp64 {adj['fp64']['ratio']:.2f}" if "fp64" in adj else ""),
+              file=sys.stderr, flush=True)
     copy_gbps = copy_bandwidth()
     cpu = None
     if not args.no_cpu:
@@ -221,6 +278,7 @@ def main():
             "fp32": {k: r32[k] for k in ("mlups", "ms_per_step", "step_gbps_model", "finite",
                                           "sum_phi_drift", "max_u", "phi_range")},
         },
+        "adjoint": adj,
         "copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
     }

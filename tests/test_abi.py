@@ -69,3 +69,33 @@ def test_create_checks_workspace_without_touching_the_device():
         B.lbm2p_step(ctx, -1)
     B.lbm2p_destroy(ctx)
     assert B.strerror(4) == "non-finite value in the state"
+
+
+def test_adjoint_workspace_and_state_checks_without_touching_the_device():
+    from paper_1812_02459_amd import binding as B
+    ok = I.base_params(64, 48)
+    p = B.make_params(ok, 0)
+    n0 = B.lbm2p_adjoint_workspace_bytes(p, 0, 64)
+    n1 = B.lbm2p_adjoint_workspace_bytes(p, 640, 64)
+    n2 = B.lbm2p_adjoint_workspace_bytes(p, 640, 8)
+    n3 = B.lbm2p_adjoint_workspace_bytes(p, 640, 32)
+    # checkpoints (22 planes each) every k steps against k per-step slots (12 planes
+    # each): the total is smallest near k = sqrt(640 * 22 / 12) ~ 34
+    assert 0 < n0 < n1 and n3 < n1 and n3 < n2
+    assert B.lbm2p_adjoint_workspace_bytes(B.make_params(ok, 1), 640, 64) < n1
+    for bad in [dict(nsteps=-1, k=4), dict(nsteps=10, k=0)]:
+        with pytest.raises(B.LBMError, match="invalid argument"):
+            B.lbm2p_adjoint_workspace_bytes(p, bad["nsteps"], bad["k"])
+    with pytest.raises(B.LBMError, match="invalid argument"):  # no adjoint of the compact filter
+        B.lbm2p_adjoint_workspace_bytes(B.make_params(dict(ok, compact=True), 0), 10, 4)
+    need = B.lbm2p_workspace_bytes(p)
+    buf = ctypes.create_string_buffer(need + 512)
+    aligned = (ctypes.addressof(buf) + 255) // 256 * 256
+    ctx = B.lbm2p_create(p, aligned, need, None)           # host-side only
+    with pytest.raises(B.LBMError, match="call out of order"):
+        B.lbm2p_record(ctx, 4, 2, aligned, need)           # before init
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_record(ctx, 4, 0, aligned, need)
+    with pytest.raises(B.LBMError, match="call out of order"):
+        B.lbm2p_adjoint(ctx, B.AdjointIO())                # nothing recorded
+    B.lbm2p_destroy(ctx)

@@ -36,14 +36,16 @@ def step_values(K):
 
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_collide_bubbles4096_hbm_traffic.md")
-KERNEL_SOURCES = ["lbm2p_kernels.h", "lbm2p_math.h", "lbm2p_impl.h", "lbm2p_f32.hip"]
+# what determines the collide kernel's code and launch shape: its source and
+# helpers (tile shapes included) and the compiler flags
+KERNEL_SOURCES = ["csrc/lbm2p_kernels.h", "csrc/lbm2p_math.h", "build.py"]
 
 
 def kernel_source_hash():
     import hashlib
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1812_02459_amd", "csrc", name), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_1812_02459_amd", name), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
 
@@ -72,7 +74,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-side", type=int, default=1024, help="CPU sample window side")
-    ap.add_argument("--cpu-steps", type=int, default=16)
+    ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adj-steps", type=int, default=640, help="steps of the adjoint timing")
     return ap.parse_args()

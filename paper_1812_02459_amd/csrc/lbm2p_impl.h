@@ -196,12 +196,6 @@ __global__ __launch_bounds__(RED_NT) void k_reduce2(const double* part, int nb, 
 
 constexpr int RED_BLOCKS = 1024;
 
-// tile shapes (nodes per workgroup of 256 threads)
-constexpr int FD_TX = 64, FD_TY = 16;
-constexpr int VEL_TX = 64, VEL_TY = 8;
-constexpr int FIL_TX = 64, FIL_TY = 16;
-constexpr int COL_TX = 64, COL_TY = 8;
-
 inline long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
 
 }  // namespace

@@ -16,6 +16,12 @@
 
 namespace lbm2p {
 
+// tile shapes of the step's kernels (nodes per workgroup of 256 threads)
+constexpr int FD_TX = 64, FD_TY = 16;
+constexpr int VEL_TX = 64, VEL_TY = 8;
+constexpr int FIL_TX = 64, FIL_TY = 16;
+constexpr int COL_TX = 64, COL_TY = 8;
+
 template <typename T>
 struct KParams {
   int nx, ny, wx, wy;
@@ -30,13 +36,16 @@ struct KParams {
 
 // ---------------------------------------------------------------- boundaries
 // Map an extended-lattice index to a node: periodic wrap, or the half-way
-// mirror (node -1-i below 0, 2n-1-i above n-1) with a parity flip.  Indices
-// further out than the ghost depth never feed an in-domain output; they are
-// clamped to stay in bounds.
+// mirror (node -1-i below 0, 2n-1-i above n-1) with a parity flip.  Ghosts feed
+// in-domain outputs only within the deepest halo (6 nodes, less than the
+// smallest lattice side 16), so one wrap or one reflection suffices; indices
+// further out (windows of ragged tiles on small lattices) feed no in-domain
+// output and are clamped to stay in bounds.  No integer division: this runs
+// once per element of every LDS window.
 __device__ __forceinline__ int map_idx(int i, int n, int wall, int& flip) {
   if (!wall) {
-    int r = i % n;
-    return r < 0 ? r + n : r;
+    i = i < 0 ? i + n : (i >= n ? i - n : i);
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
   }
   if (i < 0) {
     i = -1 - i;

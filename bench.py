@@ -77,6 +77,8 @@ def parse():
     ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--adj-steps", type=int, default=640, help="steps of the adjoint timing")
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="only the adjoint cost (prints its JSON object), e.g. for a kernel trace")
     return ap.parse_args()
 
 
@@ -212,6 +214,12 @@ def main():
         sys.exit(2)
     import torch
     from paper_1812_02459_amd import inputs as I
+    if args.adjoint_only:
+        res = {"fp32": adjoint_cost(1, args.adj_steps)}
+        if not args.no_fp64:
+            res["fp64"] = adjoint_cost(0, args.adj_steps)
+        print(json.dumps({"adjoint": res}), flush=True)
+        return
     t0 = time.perf_counter()
     wl = I.bubble_ensemble(n=args.n, nb=args.bubbles, seed=0, steps=args.steps)
     print(f"# workload built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)

@@ -50,19 +50,30 @@ struct AdjConst {
 // second plane of the same parity) extended through the ghosts: periodic
 // wrap, or the half-way mirror with the value multiplied by sx for an
 // x-mirror and sy for a y-mirror.
-template <typename T, int NT>
-__device__ __forceinline__ void load_par(T* dst, int RW, int RH, const T* __restrict__ src,
+template <typename T, int NT, int RW, int RH>
+__device__ __forceinline__ void load_par(T* dst, const T* __restrict__ src,
                                          const T* __restrict__ src2, int gx0, int gy0,
                                          const KParams<T>& P, int sx, int sy) {
-  for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
-    const int ly = idx / RW, lx = idx - ly * RW;
-    int fx = 0, fy = 0;
-    const int x = map_idx(gx0 + lx, P.nx, P.wx, fx);
-    const int y = map_idx(gy0 + ly, P.ny, P.wy, fy);
-    const long long o = (long long)y * P.nx + x;
-    T v = src[o];
-    if (src2) v = v + src2[o];
-    dst[idx] = ((fx && sx < 0) != (fy && sy < 0)) ? -v : v;
+  constexpr int N = RW * RH, IT = (N + NT - 1) / NT;
+  T v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int idx = (int)threadIdx.x + k * NT;
+    if (idx < N) {
+      const int ly = idx / RW, lx = idx - ly * RW;
+      int fx = 0, fy = 0;
+      const int x = map_idx(gx0 + lx, P.nx, P.wx, fx);
+      const int y = map_idx(gy0 + ly, P.ny, P.wy, fy);
+      const int o = y * P.nx + x;
+      T w = src[o];
+      if (src2) w = w + src2[o];
+      v[k] = ((fx && sx < 0) != (fy && sy < 0)) ? -w : w;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int idx = (int)threadIdx.x + k * NT;
+    if (idx < N) dst[idx] = v[k];
   }
 }
 
@@ -374,18 +385,18 @@ __global__ __launch_bounds__(NT) void k_adj_collide(
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
-  load_window<T, T, NT>(sUx, W1, H1, ux, x0 - 1, y0 - 1, P, true);
-  load_window<T, T, NT>(sUy, W1, H1, uy, x0 - 1, y0 - 1, P, true);
-  if (COUPLED) load_window<T, T, NT>(sPt, W1, H1, pt, x0 - 1, y0 - 1, P, false);
+  load_window<T, T, NT, W2, H2>(sP, phi, x0 - 2, y0 - 2, P, false);
+  load_window<T, T, NT, W1, H1>(sUx, ux, x0 - 1, y0 - 1, P, true);
+  load_window<T, T, NT, W1, H1>(sUy, uy, x0 - 1, y0 - 1, P, true);
+  if (COUPLED) load_window<T, T, NT, W1, H1>(sPt, pt, x0 - 1, y0 - 1, P, false);
   if (PEND) {
     // only real neighbours are read (a population that bounced back streamed
     // from the node itself), so the plain window suffices
-    load_window<T, T, NT>(sB, W1, H1, pphi, x0 - 1, y0 - 1, P, false);
+    load_window<T, T, NT, W1, H1>(sB, pphi, x0 - 1, y0 - 1, P, false);
     if (COUPLED) {
-      load_window<T, T, NT>(sQ, W1, H1, pp, x0 - 1, y0 - 1, P, false);
-      load_window<T, T, NT>(sJx, W1, H1, pjx, x0 - 1, y0 - 1, P, false);
-      load_window<T, T, NT>(sJy, W1, H1, pjy, x0 - 1, y0 - 1, P, false);
+      load_window<T, T, NT, W1, H1>(sQ, pp, x0 - 1, y0 - 1, P, false);
+      load_window<T, T, NT, W1, H1>(sJx, pjx, x0 - 1, y0 - 1, P, false);
+      load_window<T, T, NT, W1, H1>(sJy, pjy, x0 - 1, y0 - 1, P, false);
     }
   }
   __syncthreads();
@@ -532,9 +543,9 @@ __global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_par<T, NT>(sPt, WN, HN, Wk.lp_p, nullptr, x0 - N, y0 - N, P, 1, 1);
-  load_par<T, NT>(sUx, WN, HN, Wk.lp_ux, Uoix, x0 - N, y0 - N, P, -1, -1);
-  load_par<T, NT>(sUy, WN, HN, Wk.lp_uy, Uoiy, x0 - N, y0 - N, P, -1, -1);
+  load_par<T, NT, WN, HN>(sPt, Wk.lp_p, nullptr, x0 - N, y0 - N, P, 1, 1);
+  load_par<T, NT, WN, HN>(sUx, Wk.lp_ux, Uoix, x0 - N, y0 - N, P, -1, -1);
+  load_par<T, NT, WN, HN>(sUy, Wk.lp_uy, Uoiy, x0 - N, y0 - N, P, -1, -1);
   const Tile<T> tB0{sB[0], WB, N + 1}, tB1{sB[1], WB, N + 1};
   // pairs (x-derivative plane, y-derivative plane) with their parities and target:
   // (d ux/dx, d ux/dy) -> u_x, (d uy/dx, d uy/dy) -> u_y, grad p -> p
@@ -543,9 +554,9 @@ __global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
 #pragma unroll 1
   for (int k = 0; k < 3; ++k) {
     __syncthreads();
-    load_par<T, NT>(sB[0], WB, HB, src[2 * k], nullptr, x0 - N - 1, y0 - N - 1, P, psx[2 * k],
+    load_par<T, NT, WB, HB>(sB[0], src[2 * k], nullptr, x0 - N - 1, y0 - N - 1, P, psx[2 * k],
                     psy[2 * k]);
-    load_par<T, NT>(sB[1], WB, HB, src[2 * k + 1], nullptr, x0 - N - 1, y0 - N - 1, P,
+    load_par<T, NT, WB, HB>(sB[1], src[2 * k + 1], nullptr, x0 - N - 1, y0 - N - 1, P,
                     psx[2 * k + 1], psy[2 * k + 1]);
     __syncthreads();
     T* d = k == 0 ? sUx : (k == 1 ? sUy : sPt);
@@ -613,7 +624,7 @@ __global__ __launch_bounds__(NT) void k_adj_vel(KParams<T> P, AdjConst C, int ti
 #pragma unroll 1
     for (int k = 0; k < 4; ++k) {
       if (k) __syncthreads();
-      load_par<T, NT>(sB, W1, H1, du_sel(Wk, src, k), nullptr, x0 - 1, y0 - 1, P, psx[k], psy[k]);
+      load_par<T, NT, W1, H1>(sB, du_sel(Wk, src, k), nullptr, x0 - 1, y0 - 1, P, psx[k], psy[k]);
       __syncthreads();
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
@@ -625,9 +636,9 @@ __global__ __launch_bounds__(NT) void k_adj_vel(KParams<T> P, AdjConst C, int ti
       }
     }
   }
-  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
-  load_window<T, T, NT>(sUx, W1, H1, ukx, x0 - 1, y0 - 1, P, true);
-  load_window<T, T, NT>(sUy, W1, H1, uky, x0 - 1, y0 - 1, P, true);
+  load_window<T, T, NT, W2, H2>(sP, phi, x0 - 2, y0 - 2, P, false);
+  load_window<T, T, NT, W1, H1>(sUx, ukx, x0 - 1, y0 - 1, P, true);
+  load_window<T, T, NT, W1, H1>(sUy, uky, x0 - 1, y0 - 1, P, true);
   __syncthreads();
   const Tile<T> tP{sP, W2, 2};
   derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
@@ -696,8 +707,8 @@ __global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int ti
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
-  load_par<T, NT>(sMu, W1, H1, Wk.a_mu, nullptr, x0 - 1, y0 - 1, P, 1, 1);
+  load_window<T, T, NT, W2, H2>(sP, phi, x0 - 2, y0 - 2, P, false);
+  load_par<T, NT, W1, H1>(sMu, Wk.a_mu, nullptr, x0 - 1, y0 - 1, P, 1, 1);
   const Tile<T> tP{sP, W2, 2}, tMu{sMu, W1, 1};
   T rb[NR], ub[2][NR];
   if (COUPLED) {
@@ -710,8 +721,8 @@ __global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int ti
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
       __syncthreads();
-      load_par<T, NT>(sB[0], W2, H2, s2[2 * k], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k], p2y[2 * k]);
-      load_par<T, NT>(sB[1], W2, H2, s2[2 * k + 1], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k + 1],
+      load_par<T, NT, W2, H2>(sB[0], s2[2 * k], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k], p2y[2 * k]);
+      load_par<T, NT, W2, H2>(sB[1], s2[2 * k + 1], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k + 1],
                       p2y[2 * k + 1]);
       __syncthreads();
       for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
@@ -744,8 +755,8 @@ __global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int ti
 #pragma unroll 1
     for (int k = 0; k < 3; ++k) {
       __syncthreads();
-      load_par<T, NT>(sB[0], W1, H1, s1[2 * k], nullptr, x0 - 1, y0 - 1, P, p1x[2 * k], p1y[2 * k]);
-      load_par<T, NT>(sB[1], W1, H1, s1[2 * k + 1], nullptr, x0 - 1, y0 - 1, P, p1x[2 * k + 1],
+      load_par<T, NT, W1, H1>(sB[0], s1[2 * k], nullptr, x0 - 1, y0 - 1, P, p1x[2 * k], p1y[2 * k]);
+      load_par<T, NT, W1, H1>(sB[1], s1[2 * k + 1], nullptr, x0 - 1, y0 - 1, P, p1x[2 * k + 1],
                       p1y[2 * k + 1]);
       __syncthreads();
 #pragma unroll
@@ -810,8 +821,8 @@ __global__ __launch_bounds__(NT) void k_adj_fd(KParams<T> P, AdjConst C, int til
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, W6, H6, in, x0 - 6, y0 - 6, P, false);
-  load_par<T, NT>(sA, W5, H5, src, nullptr, x0 - 5, y0 - 5, P, 1, 1);
+  load_window<T, T, NT, W6, H6>(sP, in, x0 - 6, y0 - 6, P, false);
+  load_par<T, NT, W5, H5>(sA, src, nullptr, x0 - 5, y0 - 5, P, 1, 1);
   __syncthreads();
   const Tile<T> tP{sP, W6, 6}, tA{sA, W5, 5}, tM{sM, W5, 5};
   for (int idx = threadIdx.x; idx < W5 * H5; idx += NT) {

@@ -70,17 +70,31 @@ __device__ __forceinline__ void tile_of(int tiles_x, int& tx, int& ty) {
   tx = t - ty * tiles_x;
 }
 
-// load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS
-template <typename T, typename S, int NT>
-__device__ __forceinline__ void load_window(T* dst, int RW, int RH, const S* __restrict__ src,
-                                            int gx0, int gy0, const KParams<T>& P, bool odd) {
-  for (int idx = threadIdx.x; idx < RW * RH; idx += NT) {
-    const int ly = idx / RW, lx = idx - ly * RW;
-    int flip = 0;
-    const int x = map_idx(gx0 + lx, P.nx, P.wx, flip);
-    const int y = map_idx(gy0 + ly, P.ny, P.wy, flip);
-    T v = T(src[(long long)y * P.nx + x]);
-    dst[idx] = (odd && flip) ? -v : v;
+// Load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS.  Each
+// thread first issues all of its global loads (independent, so their latencies
+// overlap), then writes them to LDS.  Node indices fit in 32 bits (checked at
+// context creation).
+template <typename T, typename S, int NT, int RW, int RH>
+__device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, int gx0, int gy0,
+                                            const KParams<T>& P, bool odd) {
+  constexpr int N = RW * RH, IT = (N + NT - 1) / NT;
+  T v[IT];
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int idx = (int)threadIdx.x + k * NT;
+    if (idx < N) {
+      const int ly = idx / RW, lx = idx - ly * RW;
+      int flip = 0;
+      const int x = map_idx(gx0 + lx, P.nx, P.wx, flip);
+      const int y = map_idx(gy0 + ly, P.ny, P.wy, flip);
+      const T w = T(src[y * P.nx + x]);
+      v[k] = (odd && flip) ? -w : w;
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < IT; ++k) {
+    const int idx = (int)threadIdx.x + k * NT;
+    if (idx < N) dst[idx] = v[k];
   }
 }
 
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(256) void k_fd(KParams<T> P, int tiles_x, const T* 
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, W5, H5, in, x0 - 5, y0 - 5, P, false);
+  load_window<T, T, NT, W5, H5>(sP, in, x0 - 5, y0 - 5, P, false);
   __syncthreads();
   const Tile<T> tP{sP, W5, 5}, tM{sM, W4, 4}, tJx{sJx, W2, 2}, tJy{sJy, W2, 2};
   for (int idx = threadIdx.x; idx < W4 * H4; idx += NT) {
@@ -309,9 +323,9 @@ __global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T*
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, WP, HPH, phi, x0 - HP, y0 - HP, P, false);
-  load_window<T, T, NT>(sU[0][0], WD, HD, uxi, x0 - KS, y0 - KS, P, true);
-  load_window<T, T, NT>(sU[0][1], WD, HD, uyi, x0 - KS, y0 - KS, P, true);
+  load_window<T, T, NT, WP, HPH>(sP, phi, x0 - HP, y0 - HP, P, false);
+  load_window<T, T, NT, WD, HD>(sU[0][0], uxi, x0 - KS, y0 - KS, P, true);
+  load_window<T, T, NT, WD, HD>(sU[0][1], uyi, x0 - KS, y0 - KS, P, true);
   __syncthreads();
   const Tile<T> tP{sP, WP, HP};
   for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
@@ -398,9 +412,9 @@ __global__ __launch_bounds__(256) void k_filter(KParams<T> P, int tiles_x, const
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(s0, WN, HN, pin, x0 - N, y0 - N, P, false);
-  load_window<T, T, NT>(s1, WN, HN, uxin, x0 - N, y0 - N, P, true);
-  load_window<T, T, NT>(s2, WN, HN, uyin, x0 - N, y0 - N, P, true);
+  load_window<T, T, NT, WN, HN>(s0, pin, x0 - N, y0 - N, P, false);
+  load_window<T, T, NT, WN, HN>(s1, uxin, x0 - N, y0 - N, P, true);
+  load_window<T, T, NT, WN, HN>(s2, uyin, x0 - N, y0 - N, P, true);
   __syncthreads();
   T d[N + 1];
 #pragma unroll
@@ -445,10 +459,10 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, int tiles_x, T* _
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT>(sP, W2, H2, phi, x0 - 2, y0 - 2, P, false);
-  load_window<T, T, NT>(sUx, W1, H1, ux, x0 - 1, y0 - 1, P, true);
-  load_window<T, T, NT>(sUy, W1, H1, uy, x0 - 1, y0 - 1, P, true);
-  if (COUPLED) load_window<T, T, NT>(sPt, W1, H1, pt, x0 - 1, y0 - 1, P, false);
+  load_window<T, T, NT, W2, H2>(sP, phi, x0 - 2, y0 - 2, P, false);
+  load_window<T, T, NT, W1, H1>(sUx, ux, x0 - 1, y0 - 1, P, true);
+  load_window<T, T, NT, W1, H1>(sUy, uy, x0 - 1, y0 - 1, P, true);
+  if (COUPLED) load_window<T, T, NT, W1, H1>(sPt, pt, x0 - 1, y0 - 1, P, false);
   __syncthreads();
   const Tile<T> tP{sP, W2, 2};
   if (COUPLED) {

@@ -364,7 +364,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         // (FP64: one sweep per launch -- the two-sweep kernel's LDS footprint
         // costs more occupancy than its saved traffic is worth in double)
         if (sizeof(T) == 4 && p.K - done >= 2 && !c->rec) {
-          k_vel<T, 2, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(
+          k_vel2<T, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(
               K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
           done += 2;
         } else {

@@ -399,6 +399,142 @@ __global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T*
   }
 }
 
+// Two velocity sweeps in one launch, for the FP32 step.  phi and p are fixed
+// during the sweeps, so F_p + F_s, J = c_J grad mu, grad rho, nu and rho are the
+// same in both: they are evaluated once per node of the tile grown by one and
+// kept in registers; the second sweep re-evaluates only the u-dependent F_nu and
+// F_m (F summed in the order (((F_p + F_s) + F_nu) + F_m) + F_g as in
+// node_force).  Each thread owns the same nodes in both sweeps.
+template <typename T, int TX, int TY>
+__global__ __launch_bounds__(256) void k_vel2(KParams<T> P, int tiles_x, const T* __restrict__ phi,
+                                              const T* __restrict__ praw, const T* __restrict__ jx,
+                                              const T* __restrict__ jy, const T* __restrict__ uxi,
+                                              const T* __restrict__ uyi, T* __restrict__ uxo,
+                                              T* __restrict__ uyo) {
+  constexpr int NT = 256;
+  constexpr int WP = TX + 6, HPH = TY + 6;   // phi, halo 3
+  constexpr int WD = TX + 4, HD = TY + 4;    // derived fields and u^0, halo 2
+  constexpr int W1 = TX + 2, H1 = TY + 2;    // first sweep and u^1, halo 1
+  constexpr int NR = (W1 * H1 + NT - 1) / NT;
+  __shared__ T sP[WP * HPH];
+  __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
+  __shared__ T sU0x[WD * HD], sU0y[WD * HD], sU1x[W1 * H1], sU1y[W1 * H1];
+  int bx, by;
+  tile_of(tiles_x, bx, by);
+  const int x0 = bx * TX, y0 = by * TY;
+  load_window<T, T, NT, WP, HPH>(sP, phi, x0 - 3, y0 - 3, P, false);
+  load_window<T, T, NT, WD, HD>(sU0x, uxi, x0 - 2, y0 - 2, P, true);
+  load_window<T, T, NT, WD, HD>(sU0y, uyi, x0 - 2, y0 - 2, P, true);
+  __syncthreads();
+  const Tile<T> tP{sP, WP, 3};
+  for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
+    const int ly = idx / WD - 2, lx = idx % WD - 2;
+    T gx, gy;
+    iso_grad<T>(tP, lx, ly, gx, gy);
+    sPx[idx] = gx;
+    sPy[idx] = gy;
+    sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
+    sRho[idx] = density<T>(tP(lx, ly), P.rho1, P.rho2);
+  }
+  __syncthreads();
+  const Tile<T> tPx{sPx, WD, 2}, tPy{sPy, WD, 2}, tMu{sMu, WD, 2}, tRho{sRho, WD, 2},
+      tU0x{sU0x, WD, 2}, tU0y{sU0y, WD, 2}, tU1x{sU1x, W1, 1}, tU1y{sU1y, W1, 1};
+  // per owned node: F_p + F_s (2), J (2), grad rho (2), nu, rho, j (2)
+  T cFx[NR], cFy[NR], cJx[NR], cJy[NR], cgx[NR], cgy[NR], cnu[NR], crho[NR], cjx[NR], cjy[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx >= W1 * H1) continue;
+    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+    const int gxn = x0 + lx, gyn = y0 + ly;
+    // ghosts beyond a wall are filled below from their mirror node
+    if ((P.wx && (gxn < 0 || gxn >= P.nx)) || (P.wy && (gyn < 0 || gyn >= P.ny))) continue;
+    int flip = 0;
+    const int x = map_idx(gxn, P.nx, P.wx, flip);
+    const int y = map_idx(gyn, P.ny, P.wy, flip);
+    const int id = y * P.nx + x;
+    const T p = praw[id];
+    cjx[r] = jx[id];
+    cjy[r] = jy[id];
+    const T ph = tP(lx, ly);
+    const T rho = density<T>(ph, P.rho1, P.rho2);
+    const T nu = kin_visc<T>(ph, rho, P.mu1, P.mu2);
+    T dmx, dmy;
+    iso_grad<T>(tMu, lx, ly, dmx, dmy);
+    const T dxyy = iso_grad_x<T>(ProdYY<T>{tPy}, lx, ly);
+    T dxxy, dyxy;
+    iso_grad<T>(ProdXY<T>{tPx, tPy}, lx, ly, dxxy, dyxy);
+    const T dyxx = iso_grad_y<T>(ProdXX<T>{tPx}, lx, ly);
+    T grx, gry;
+    iso_grad<T>(tRho, lx, ly, grx, gry);
+    cFx[r] = (-p) * grx + P.kappa * (dxyy - dyxy);
+    cFy[r] = (-p) * gry + P.kappa * (dyxx - dxxy);
+    cJx[r] = P.cJ * dmx;
+    cJy[r] = P.cJ * dmy;
+    cgx[r] = grx;
+    cgy[r] = gry;
+    cnu[r] = nu;
+    crho[r] = rho;
+    // first sweep from u^0
+    T duxx, duxy, duyx, duyy;
+    iso_grad<T>(tU0x, lx, ly, duxx, duxy);
+    iso_grad<T>(tU0y, lx, ly, duyx, duyy);
+    const T Sxx = duxx + duxx, Sxy = duyx + duxy, Syy = duyy + duyy;
+    const T Fx = ((cFx[r] + nu * (Sxx * grx + Sxy * gry)) + (cJx[r] * duxx + cJy[r] * duxy)) +
+                 (rho - P.rho_ref) * P.gx;
+    const T Fy = ((cFy[r] + nu * (Sxy * grx + Syy * gry)) + (cJx[r] * duyx + cJy[r] * duyy)) +
+                 (rho - P.rho_ref) * P.gy;
+    sU1x[idx] = cjx[r] + Fx / (T(2) * rho);
+    sU1y[idx] = cjy[r] + Fy / (T(2) * rho);
+  }
+  __syncthreads();
+  if (P.wx || P.wy) {
+    // no-slip ghosts of u^1: the mirror node's value, sign flipped once per
+    // mirrored axis (as the oracle's ghost extension does)
+    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
+      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+      const int gxn = x0 + lx, gyn = y0 + ly;
+      int mx = gxn, my = gyn, flips = 0;
+      if (P.wx && gxn < 0) { mx = -1 - gxn; flips ^= 1; }
+      if (P.wx && gxn >= P.nx) { mx = 2 * P.nx - 1 - gxn; flips ^= 1; }
+      if (P.wy && gyn < 0) { my = -1 - gyn; flips ^= 1; }
+      if (P.wy && gyn >= P.ny) { my = 2 * P.ny - 1 - gyn; flips ^= 1; }
+      if (mx == gxn && my == gyn) continue;            // not a ghost
+      const int lmx = mx - x0, lmy = my - y0;
+      if (lmx < -1 || lmx >= TX + 1 || lmy < -1 || lmy >= TY + 1) {
+        sU1x[idx] = T(0);                              // never read by an in-domain output
+        sU1y[idx] = T(0);
+        continue;
+      }
+      const int om = (lmy + 1) * W1 + (lmx + 1);
+      sU1x[idx] = flips ? -sU1x[om] : sU1x[om];
+      sU1y[idx] = flips ? -sU1y[om] : sU1y[om];
+    }
+    __syncthreads();
+  }
+  // second sweep from u^1 on the tile
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    if (idx >= W1 * H1) continue;
+    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+    if (lx < 0 || lx >= TX || ly < 0 || ly >= TY) continue;
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= P.nx || y >= P.ny) continue;
+    T duxx, duxy, duyx, duyy;
+    iso_grad<T>(tU1x, lx, ly, duxx, duxy);
+    iso_grad<T>(tU1y, lx, ly, duyx, duyy);
+    const T Sxx = duxx + duxx, Sxy = duyx + duxy, Syy = duyy + duyy;
+    const T Fx = ((cFx[r] + cnu[r] * (Sxx * cgx[r] + Sxy * cgy[r])) +
+                  (cJx[r] * duxx + cJy[r] * duxy)) + (crho[r] - P.rho_ref) * P.gx;
+    const T Fy = ((cFy[r] + cnu[r] * (Sxy * cgx[r] + Syy * cgy[r])) +
+                  (cJx[r] * duyx + cJy[r] * duyy)) + (crho[r] - P.rho_ref) * P.gy;
+    const int id = y * P.nx + x;
+    uxo[id] = cjx[r] + Fx / (T(2) * crho[r]);
+    uyo[id] = cjy[r] + Fy / (T(2) * crho[r]);
+  }
+}
+
 // ------------------------------------------------ a4: explicit selective filter
 // chi <- chi - a [ sum_j d_|j| chi(x+j, y) + sum_j d_|j| chi(x, y+j) ]  (eq:filter)
 template <typename T, int N, int TX, int TY>

@@ -100,6 +100,7 @@ int lbm2p_workspace_bytes(const lbm2p_params* p, size_t* bytes);
  * 9 * nx * ny (rounded up to 64) >= 2^31 (population slots use 32-bit offsets),
  * rho <= 0, mu < 0, W <= 0, M < 0, tau_f <= 1/2, any s outside [0, 2], a filter
  * order not in {0,5,7,9,11}, compact_n outside 1..5, |compact_alpha| >= 1/2,
+ * a compact filter on a lattice side above 7680 (its line solve holds a line in LDS),
  * K outside 1..8, filter_a outside [0,1], eps < 0, a wall axis shorter than the
  * ghost depth; ENOSPACE for a small workspace; EHIP if an event cannot be made. */
 int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes,

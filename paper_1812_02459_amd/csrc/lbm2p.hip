@@ -39,6 +39,8 @@ int validate(const lbm2p_params* p) {
   if (p->compact != 0 && p->compact != 1) return LBM2P_EINVAL;
   if (p->compact && (p->compact_n < 1 || p->compact_n > 5)) return LBM2P_EINVAL;
   if (p->compact && !(p->compact_alpha > -0.5 && p->compact_alpha < 0.5)) return LBM2P_EINVAL;
+  // the compact filter's line solve stages a whole line in LDS
+  if (p->compact && (p->nx > 7680 || p->ny > 7680)) return LBM2P_EINVAL;
   if (p->K < 1 || p->K > 8) return LBM2P_EINVAL;
   if (!(p->filter_a >= 0 && p->filter_a <= 1)) return LBM2P_EINVAL;
   if (p->coupled != 0 && p->coupled != 1) return LBM2P_EINVAL;
@@ -59,7 +61,8 @@ size_t compact_planes(const lbm2p_params* p) { return (p->coupled && p->compact)
 
 size_t compact_table_doubles(const lbm2p_params* p) {
   if (!(p->coupled && p->compact)) return 0;
-  return 2 * 3 * ((size_t)p->nx + (size_t)p->ny);  // 2 parities x (cp, inv, z) per axis
+  // 2 parities x (cp, inv, z) per axis, then 3 per-line factors per line
+  return 2 * 3 * ((size_t)p->nx + (size_t)p->ny) + 3 * ((size_t)p->nx + (size_t)p->ny);
 }
 
 size_t ws_size(const lbm2p_params* p) {
@@ -102,7 +105,7 @@ void compact_coeffs(int N, double alpha, double* a) {
 // nodes: periodic -> cyclic matrix split as B + u v^T (Sherman-Morrison with
 // gamma = -1); wall -> end rows 1 + sgn alpha (mirror ghosts).
 void compact_table(int n, double alpha, bool cyclic, double sgn, double* cp, double* inv,
-                   double* z, double* fac, double* den) {
+                   double* z, double* fac, double* den, int* flat) {
   std::vector<double> b(n, 1.0);
   double gamma = 0;
   if (cyclic) {
@@ -120,6 +123,12 @@ void compact_table(int n, double alpha, bool cyclic, double sgn, double* cp, dou
     cp[i] = alpha * inv[i];
     c_prev = cp[i];
   }
+  // c'_i and 1/pivot_i depend on rows 0..i only and converge to fixed values;
+  // from index *flat up to n - 2 they equal the values at *flat bit for bit
+  // (only the last row differs), so the device need not read them there
+  int K = n - 1;
+  while (K > 0 && cp[K - 1] == cp[n - 2] && inv[K - 1] == inv[n - 2]) --K;
+  *flat = n >= 2 ? K : 0;
   if (cyclic) {
     // B z = u with u = (gamma, 0, ..., 0, alpha)
     std::vector<double> d(n);
@@ -221,9 +230,11 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   c->cscratch = compact_planes(p) ? take((long long)compact_planes(p)) : nullptr;
   c->red = (double*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
   c->ctab_dev = nullptr;
+  c->cfct = nullptr;
   c->ctab_uploaded = 0;
   if (compact_table_doubles(p)) {
     c->ctab_dev = c->red + (RED_BLOCKS + 1) * RED_K;
+    c->cfct = c->ctab_dev + 2 * 3 * ((size_t)p->nx + (size_t)p->ny);
     c->ctab_host.assign(compact_table_doubles(p), 0.0);
     compact_coeffs(p->compact_n, p->compact_alpha, c->ca);
     size_t off = 0;
@@ -235,7 +246,7 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
         c->ctab_off[axis][par] = off;
         double* base = c->ctab_host.data() + off;
         compact_table(n, p->compact_alpha, cyclic, par ? -1.0 : 1.0, base, base + n, base + 2 * n,
-                      &c->cfac[axis][par], &c->cden[axis][par]);
+                      &c->cfac[axis][par], &c->cden[axis][par], &c->cflat[axis][par]);
         off += 3 * (size_t)n;
       }
     }

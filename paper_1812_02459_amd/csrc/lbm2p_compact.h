@@ -6,13 +6,22 @@
 // The a_n solve T(0) = 1, T(pi) = 0 and the flatness conditions of the transfer
 // function T(w) = sum a_n cos(n w) / (1 + 2 alpha cos w) (host side, lbm2p.hip).
 //
-// Lines are solved with the Thomas algorithm on tables precomputed on the host
-// for the constant-coefficient matrix (c'_i and 1/pivot_i); a periodic line is
-// the cyclic matrix, solved by Sherman-Morrison with a precomputed correction
-// vector z.  Beyond a wall the right-hand side uses the half-way mirror ghosts
-// (sign kept for p, flipped for u) and the matrix's end rows fold the ghost
-// F_{-1} = +-F_0 into the diagonal.  One thread per (line, field); the right-hand
-// side comes from a sliding window of 2N+1 values held in registers.
+// The line matrix is factorised once on the host (Thomas: c'_i and 1/pivot_i);
+// a periodic line is the cyclic matrix, solved by Sherman-Morrison with a
+// precomputed correction vector z.  Beyond a wall the right-hand side uses the
+// half-way mirror ghosts (sign kept for p, flipped for u) and the matrix's end
+// rows fold the ghost F_{-1} = +-F_0 into the diagonal.
+//
+// Parallel line solve.  The forward and backward Thomas sweeps are first-order
+// linear recurrences,  d_i = (-alpha/piv_i) d_{i-1} + r_i/piv_i  and
+// y_i = -c'_i y_{i+1} + d_i.  One wavefront takes one (line, field); each of its
+// 64 lanes owns a contiguous chunk of the line, composes its chunk's affine map
+// x -> A x + B, and a 6-step shuffle scan over the lanes gives every chunk the
+// value entering it; a second pass over the chunk then produces the values.
+// x-lines (contiguous rows) are staged in LDS; y-lines are taken 64 columns at
+// a time, each column split into chunks over the waves of a workgroup.  The
+// periodic lines' Sherman-Morrison correction x_i = y_i - f z_i (f per line)
+// is applied where F is consumed.
 #pragma once
 
 #include "lbm2p_kernels.h"
@@ -20,15 +29,27 @@
 namespace lbm2p {
 
 // Table layout per (axis, parity): cp[n] (c'), inv[n] (1/pivot), z[n] (cyclic
-// correction, periodic lines only), then scalar vz = v.z denominators folded in
-// by the host: fac = beta/gamma, den = 1 + z_0 + fac z_{n-1}.
+// correction, periodic lines only), and the scalars fac = beta/gamma,
+// den = 1 + z_0 + fac z_{n-1} of the Sherman-Morrison denominator.
 struct CompactLine {
   const double* cp;
   const double* inv;
   const double* z;
   double fac, den;
   int cyclic;
+  int K;                   // c'_i, 1/pivot_i equal cp_lim, inv_lim for K <= i <= n - 2
+  double cp_lim, inv_lim;
 };
+
+// table entries, read only outside their constant run
+template <typename T>
+__device__ __forceinline__ T cl_inv(const CompactLine& L, int i, int n) {
+  return (i < L.K || i == n - 1) ? T(L.inv[i]) : T(L.inv_lim);
+}
+template <typename T>
+__device__ __forceinline__ T cl_cp(const CompactLine& L, int i, int n) {
+  return (i < L.K || i == n - 1) ? T(L.cp[i]) : T(L.cp_lim);
+}
 
 template <typename T>
 struct CompactArgs {
@@ -47,87 +68,295 @@ __device__ __forceinline__ T line_val(const T* __restrict__ f, long long b, long
   return (odd && flip) ? -v : v;
 }
 
-// One line solve: F = A^{-1} r for the line through base b with stride s.
-// Writes F into out (same indexing).  Scratch d holds the forward sweep.
-template <typename T, int N>
-__device__ __forceinline__ void compact_line(const T* __restrict__ f, T* __restrict__ d,
-                                             T* __restrict__ out, long long b, long long s, int n,
-                                             int wall, bool odd, const CompactArgs<T>& A,
-                                             const CompactLine& L) {
-  T w[2 * N + 1];
+// x -> a x + b
+template <typename T>
+struct Aff {
+  T a, b;
+};
+
+// l after e
+template <typename T>
+__device__ __forceinline__ Aff<T> aff_after(const Aff<T>& l, const Aff<T>& e) {
+  return Aff<T>{l.a * e.a, l.a * e.b + l.b};
+}
+
+// Composite of the maps of lanes 0..k-1 (UP) or k+1..63 (down), applied to 0:
+// the value entering lane k's chunk.  Hillis-Steele over the wavefront.
+template <typename T, bool UP>
+__device__ __forceinline__ T lane_carry(Aff<T> m) {
+  const int lane = (int)(threadIdx.x & 63);
 #pragma unroll
-  for (int k = 0; k < 2 * N + 1; ++k) w[k] = line_val<T>(f, b, s, k - N, n, wall, odd);
-  T a[N + 1];
+  for (int d = 1; d < 64; d <<= 1) {
+    const T oa = UP ? __shfl_up(m.a, d, 64) : __shfl_down(m.a, d, 64);
+    const T ob = UP ? __shfl_up(m.b, d, 64) : __shfl_down(m.b, d, 64);
+    const bool ok = UP ? lane >= d : lane + d < 64;
+    if (ok) m = aff_after(m, Aff<T>{oa, ob});
+  }
+  // exclusive: the neighbour's inclusive composite, applied to 0
+  const T b = UP ? __shfl_up(m.b, 1, 64) : __shfl_down(m.b, 1, 64);
+  return (UP ? lane == 0 : lane == 63) ? T(0) : b;
+}
+
+// The value entering thread t's chunk when NWV waves hold consecutive chunks
+// (t = 64 wave + lane): UP composes chunks 0..t-1, down chunks t+1..end, both
+// applied to 0.  Intra-wave scans, then the wave totals through LDS.
+template <typename T, bool UP, int NWV>
+__device__ __forceinline__ T block_carry(Aff<T> m, T* sWa, T* sWb) {
+  const int lane = (int)(threadIdx.x & 63), wv = (int)(threadIdx.x >> 6);
 #pragma unroll
-  for (int k = 0; k <= N; ++k) a[k] = T(A.a[k] / 2.0);
+  for (int d = 1; d < 64; d <<= 1) {
+    const T oa = UP ? __shfl_up(m.a, d, 64) : __shfl_down(m.a, d, 64);
+    const T ob = UP ? __shfl_up(m.b, d, 64) : __shfl_down(m.b, d, 64);
+    const bool ok = UP ? lane >= d : lane + d < 64;
+    if (ok) m = aff_after(m, Aff<T>{oa, ob});
+  }
+  // this wave's total: the inclusive composite at its last lane in the order
+  if (lane == (UP ? 63 : 0)) {
+    sWa[wv] = m.a;
+    sWb[wv] = m.b;
+  }
+  // exclusive composite within the wave (identity at the first lane)
+  T ea = UP ? __shfl_up(m.a, 1, 64) : __shfl_down(m.a, 1, 64);
+  T eb = UP ? __shfl_up(m.b, 1, 64) : __shfl_down(m.b, 1, 64);
+  if (lane == (UP ? 0 : 63)) {
+    ea = T(1);
+    eb = T(0);
+  }
+  __syncthreads();
+  T c = T(0);
+  if (UP) {
+    for (int k = 0; k < wv; ++k) c = sWa[k] * c + sWb[k];
+  } else {
+    for (int k = NWV - 1; k > wv; --k) c = sWa[k] * c + sWb[k];
+  }
+  __syncthreads();
+  return ea * c + eb;
+}
+
+// Longest line the LDS-staged line solve takes (the FP64 line, padded, in 64 KB).
+constexpr int COMPACT_MAX_N = 7680;
+
+// LDS position of line element e: one pad word per chunk of 2^lg elements, so
+// that the 64 lanes walking their chunks in step hit distinct banks.
+__device__ __forceinline__ int cpad(int e, int lg) { return e + (e >> lg); }
+
+// Solve the line systems of 3 fields of rows of length n (nlines rows per
+// field, row stride n): F = A^{-1} r, written to dst.  For periodic lines the
+// Sherman-Morrison factor of each line goes to fct (the caller subtracts
+// fct z_i).  One workgroup of NWV waves per (line, field); grid = 3 * nlines;
+// dynamic LDS of (n + (n >> lg) + 1) elements.  The right-hand side is formed
+// and the result written in coalesced passes over the line; the recurrences
+// run on LDS in chunks of 2^lg elements per thread.
+template <typename T, int N, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_cline(CompactArgs<T> A, CompactLine Le,
+                                                    CompactLine Lo, const T* __restrict__ s0,
+                                                    const T* __restrict__ s1,
+                                                    const T* __restrict__ s2, T* __restrict__ d0,
+                                                    T* __restrict__ d1, T* __restrict__ d2,
+                                                    double* __restrict__ fct, int n, int nlines,
+                                                    int wall, int lg) {
+  constexpr int NTH = 64 * NWV;
+  extern __shared__ unsigned char smem_raw[];
+  T* sd = reinterpret_cast<T*>(smem_raw);
+  __shared__ T sWa[NWV], sWb[NWV];
+  const int field = (int)blockIdx.x / nlines, line = (int)blockIdx.x - field * nlines;
+  const T* src = field == 0 ? s0 : field == 1 ? s1 : s2;
+  T* out = field == 0 ? d0 : field == 1 ? d1 : d2;
+  const bool odd = field != 0;
+  const CompactLine L = odd ? Lo : Le;
+  const long long b = (long long)line * n;
+  const int t = (int)threadIdx.x;
+  const int m = 1 << lg;
+  const int i0 = t * m < n ? t * m : n, i1 = (t + 1) * m < n ? (t + 1) * m : n;
+  T ah[N + 1];
+#pragma unroll
+  for (int k = 0; k <= N; ++k) ah[k] = T(A.a[k] / 2.0);
   const T al = T(A.alpha);
-  T prev = T(0);
-  for (int i = 0; i < n; ++i) {
-    // right-hand side at i from the window w[k] = chi_{i + k - N}
-    T r = a[0] * (w[N] + w[N]);
+  // right-hand side, coalesced over the line
+#pragma unroll 2
+  for (int e = t; e < n; e += NTH) {
+    T r;
+    if (e >= N && e < n - N) {
+      const T* q = src + b + e;
+      r = ah[0] * (q[0] + q[0]);
 #pragma unroll
-    for (int k = 1; k <= N; ++k) r = r + a[k] * (w[N + k] + w[N - k]);
-    const T di = (i == 0 ? r : r - al * prev) * T(L.inv[i]);
-    d[b + s * i] = di;
-    prev = di;
+      for (int k = 1; k <= N; ++k) r = r + ah[k] * (q[k] + q[-k]);
+    } else {
+      r = ah[0] * (line_val<T>(src, b, 1, e, n, wall, odd) + line_val<T>(src, b, 1, e, n, wall, odd));
 #pragma unroll
-    for (int k = 0; k < 2 * N; ++k) w[k] = w[k + 1];
-    w[2 * N] = line_val<T>(f, b, s, i + N + 1, n, wall, odd);
+      for (int k = 1; k <= N; ++k)
+        r = r + ah[k] * (line_val<T>(src, b, 1, e + k, n, wall, odd) +
+                         line_val<T>(src, b, 1, e - k, n, wall, odd));
+    }
+    sd[cpad(e, lg)] = r;
   }
-  // back substitution; y_{n-1} = d_{n-1}
-  T y = prev;
-  out[b + s * (n - 1)] = y;
-  const T ylast = y;
-  for (int i = n - 2; i >= 0; --i) {
-    y = d[b + s * i] - T(L.cp[i]) * y;
-    out[b + s * i] = y;
+  __syncthreads();
+  // forward sweep: compose, scan, replay (d_i in place of r_i)
+  Aff<T> M{T(1), T(0)};
+  for (int i = i0; i < i1; ++i) {
+    const T inv = cl_inv<T>(L, i, n);
+    M = aff_after(Aff<T>{-(al * inv), sd[cpad(i, lg)] * inv}, M);
   }
-  if (L.cyclic) {
-    // Sherman-Morrison: x = y - (y_0 + fac y_{n-1}) / den * z
-    const T fct = (y + T(L.fac) * ylast) / T(L.den);
-    for (int i = 0; i < n; ++i) out[b + s * i] = out[b + s * i] - fct * T(L.z[i]);
+  T d = block_carry<T, true, NWV>(M, sWa, sWb);
+  for (int i = i0; i < i1; ++i) {
+    const int o = cpad(i, lg);
+    d = (sd[o] - al * d) * cl_inv<T>(L, i, n);
+    sd[o] = d;
+  }
+  // backward sweep: compose from the chunk's end, scan from the last thread, replay
+  Aff<T> Mb{T(1), T(0)};
+  for (int i = i1 - 1; i >= i0; --i) Mb = aff_after(Aff<T>{-cl_cp<T>(L, i, n), sd[cpad(i, lg)]}, Mb);
+  T y = block_carry<T, false, NWV>(Mb, sWa, sWb);
+  for (int i = i1 - 1; i >= i0; --i) {
+    const int o = cpad(i, lg);
+    y = sd[o] - cl_cp<T>(L, i, n) * y;
+    sd[o] = y;
+  }
+  __syncthreads();
+  for (int e = t; e < n; e += NTH) out[b + e] = sd[cpad(e, lg)];
+  if (L.cyclic && t == 0) {
+    // Sherman-Morrison: x = y - (y_0 + fac y_{n-1}) / den * z, one factor per line
+    const T y0 = sd[cpad(0, lg)], yl = sd[cpad(n - 1, lg)];
+    fct[(long long)field * nlines + line] = double((y0 + T(L.fac) * yl) / T(L.den));
   }
 }
 
-// x-lines of the three fields: Fx of (p, ux, uy) into fx[0..2]
-template <typename T, int N>
-__global__ __launch_bounds__(64) void k_compact_x(KParams<T> P, CompactArgs<T> A,
-                                                  const T* __restrict__ p, const T* __restrict__ ux,
-                                                  const T* __restrict__ uy, T* __restrict__ d,
-                                                  T* __restrict__ fx) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
-  if (t >= 3 * P.ny) return;
-  const int field = t / P.ny, y = t - field * P.ny;
-  const T* src = field == 0 ? p : field == 1 ? ux : uy;
-  const bool odd = field != 0;
-  const long long b = (long long)y * P.nx;
-  compact_line<T, N>(src, d + field * P.ps, fx + field * P.ps, b, 1, P.nx, P.wx, odd, A,
-                     A.line[0][odd ? 1 : 0]);
-}
-
-// y-lines, then the unsplit update chi - a [(chi - Fx) + (chi - Fy)]
-template <typename T, int N>
-__global__ __launch_bounds__(64) void k_compact_y(KParams<T> P, CompactArgs<T> A,
-                                                  const T* __restrict__ p, const T* __restrict__ ux,
-                                                  const T* __restrict__ uy, T* __restrict__ d,
-                                                  const T* __restrict__ fx, T* __restrict__ fy,
-                                                  T* __restrict__ po, T* __restrict__ uxo,
-                                                  T* __restrict__ uyo) {
-  const int t = blockIdx.x * 64 + threadIdx.x;
-  if (t >= 3 * P.nx) return;
-  const int field = t / P.nx, x = t - field * P.nx;
-  const T* src = field == 0 ? p : field == 1 ? ux : uy;
-  T* dst = field == 0 ? po : field == 1 ? uxo : uyo;
-  const bool odd = field != 0;
-  T* fyf = fy + field * P.ps;
-  const T* fxf = fx + field * P.ps;
-  compact_line<T, N>(src, d + field * P.ps, fyf, x, P.nx, P.ny, P.wy, odd, A,
-                     A.line[1][odd ? 1 : 0]);
+// y-lines and the update.  Lanes are 64 adjacent columns (coalesced rows);
+// the NW waves of a workgroup split each column into NW chunks, exchange their
+// chunks' affine maps through LDS, and replay.  The right-hand side comes from
+// a sliding window of 2N+1 values per column; d and y go through a scratch
+// plane.  The last pass forms chi~ = chi - a [(chi - F_x) + (chi - F_y)] with
+// both directions' Sherman-Morrison corrections.  grid = (column blocks, 3).
+template <typename T, int N, int NW>
+__global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T> A,
+                                                     const T* __restrict__ c0,
+                                                     const T* __restrict__ c1,
+                                                     const T* __restrict__ c2,
+                                                     const T* __restrict__ fx, T* __restrict__ scr,
+                                                     const double* __restrict__ fctx,
+                                                     T* __restrict__ o0, T* __restrict__ o1,
+                                                     T* __restrict__ o2) {
+  __shared__ T sA[NW][64], sB[NW][64];
+  __shared__ T sY0[64], sYl[64];
+  const int f = (int)blockIdx.y;
+  const bool odd = f != 0;
+  const T* src = f == 0 ? c0 : f == 1 ? c1 : c2;
+  T* dst = f == 0 ? o0 : f == 1 ? o1 : o2;
+  T* sc = scr + (long long)f * P.ps;
+  const T* fxf = fx + (long long)f * P.ps;
+  const CompactLine L = odd ? A.line[1][1] : A.line[1][0];
+  const CompactLine Lx = odd ? A.line[0][1] : A.line[0][0];
+  const int nx = P.nx, n = P.ny;
+  const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+  const int x = (int)blockIdx.x * 64 + lane;
+  const bool live = x < nx;
+  // idle lanes (beyond the last column) read a real column and write nothing
+  const int xs = live ? x : nx - 1;
+  const int m = (n + NW - 1) / NW;
+  const int i0 = w * m < n ? w * m : n, i1 = (w + 1) * m < n ? (w + 1) * m : n;
+  T ah[N + 1];
+#pragma unroll
+  for (int k = 0; k <= N; ++k) ah[k] = T(A.a[k] / 2.0);
+  const T al = T(A.alpha);
+  // window[k] = chi(x, i + k - N)
+  T win[2 * N + 1];
+  auto load_win = [&](int i) {
+#pragma unroll
+    for (int k = 0; k < 2 * N + 1; ++k) win[k] = line_val<T>(src, xs, nx, i + k - N, n, P.wy, odd);
+  };
+  auto rhs = [&]() {
+    T r = ah[0] * (win[N] + win[N]);
+#pragma unroll
+    for (int k = 1; k <= N; ++k) r = r + ah[k] * (win[N + k] + win[N - k]);
+    return r;
+  };
+  // The serial passes take the next CB window values / scratch values in one
+  // batch of independent loads, so that their latency is paid once per batch.
+  constexpr int CB = 8;
+  // forward sweep
+  Aff<T> M{T(1), T(0)};
+  if (i0 < i1) load_win(i0);
+  for (int base = i0; base < i1; base += CB) {
+    T nv[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) nv[j] = line_val<T>(src, xs, nx, base + j + 1 + N, n, P.wy, odd);
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      if (base + j < i1) {
+        const T inv = cl_inv<T>(L, base + j, n);
+        M = aff_after(Aff<T>{-(al * inv), rhs() * inv}, M);
+#pragma unroll
+        for (int k = 0; k < 2 * N; ++k) win[k] = win[k + 1];
+        win[2 * N] = nv[j];
+      }
+    }
+  }
+  sA[w][lane] = M.a;
+  sB[w][lane] = M.b;
+  __syncthreads();
+  T d = T(0);
+  for (int k = 0; k < w; ++k) d = sA[k][lane] * d + sB[k][lane];
+  __syncthreads();
+  if (i0 < i1) load_win(i0);
+  for (int base = i0; base < i1; base += CB) {
+    T nv[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) nv[j] = line_val<T>(src, xs, nx, base + j + 1 + N, n, P.wy, odd);
+#pragma unroll
+    for (int j = 0; j < CB; ++j) {
+      if (base + j < i1) {
+        d = (rhs() - al * d) * cl_inv<T>(L, base + j, n);
+        if (live) sc[(long long)(base + j) * nx + xs] = d;
+#pragma unroll
+        for (int k = 0; k < 2 * N; ++k) win[k] = win[k + 1];
+        win[2 * N] = nv[j];
+      }
+    }
+  }
+  // backward sweep
+  Aff<T> Mb{T(1), T(0)};
+  for (int top = i1 - 1; top >= i0; top -= CB) {
+    T v[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (top - j >= i0) v[j] = sc[(long long)(top - j) * nx + xs];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (top - j >= i0) Mb = aff_after(Aff<T>{-cl_cp<T>(L, top - j, n), v[j]}, Mb);
+  }
+  sA[w][lane] = Mb.a;
+  sB[w][lane] = Mb.b;
+  __syncthreads();
+  T y = T(0);
+  for (int k = NW - 1; k > w; --k) y = sA[k][lane] * y + sB[k][lane];
+  for (int top = i1 - 1; top >= i0; top -= CB) {
+    T v[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (top - j >= i0) v[j] = sc[(long long)(top - j) * nx + xs];
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (top - j >= i0) {
+        const int i = top - j;
+        y = v[j] - cl_cp<T>(L, i, n) * y;
+        if (live) sc[(long long)i * nx + xs] = y;
+        if (i == n - 1) sYl[lane] = y;
+        if (i == 0) sY0[lane] = y;
+      }
+  }
+  __syncthreads();
+  T fct = T(0);
+  if (L.cyclic) fct = (sY0[lane] + T(L.fac) * sYl[lane]) / T(L.den);
+  if (!live) return;
   const T a = P.fa;
-  for (int y = 0; y < P.ny; ++y) {
-    const long long id = (long long)y * P.nx + x;
-    const T c = src[id];
-    dst[id] = c - a * ((c - fxf[id]) + (c - fyf[id]));
+  for (int i = i0; i < i1; ++i) {
+    const long long o = (long long)i * nx + x;
+    T fy = sc[o];
+    if (L.cyclic) fy = fy - fct * T(L.z[i]);
+    T fxv = fxf[o];
+    if (Lx.cyclic) fxv = fxv - T(fctx[(long long)f * n + i]) * T(Lx.z[x]);
+    const T ch = src[o];
+    dst[o] = ch - a * ((ch - fxv) + (ch - fy));
   }
 }
 

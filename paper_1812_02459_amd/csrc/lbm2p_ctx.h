@@ -34,9 +34,11 @@ struct lbm2p_ctx {
   // the workspace (device) and their host image, coefficients a_n
   void* cscratch;
   double* ctab_dev;
+  double* cfct;  // per-line Sherman-Morrison factors (3 ny x-lines, 3 nx y-lines)
   std::vector<double> ctab_host;
   double ca[6];
   double cfac[2][2], cden[2][2];
+  int cflat[2][2];        // first index of the tables' constant run (per axis, parity)
   size_t ctab_off[2][2];  // offsets (in doubles) of each (axis, parity) table
   int ctab_n[2];
   int ctab_uploaded;

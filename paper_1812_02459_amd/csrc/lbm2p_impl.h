@@ -272,9 +272,12 @@ CompactArgs<T> compact_args(const lbm2p_ctx* c) {
     for (int par = 0; par < 2; ++par) {
       const int n = c->ctab_n[axis];
       const double* base = c->ctab_dev + c->ctab_off[axis][par];
+      const int K = c->cflat[axis][par];
+      const double* h = c->ctab_host.data() + c->ctab_off[axis][par];
       A.line[axis][par] = CompactLine{base, base + n, base + 2 * n, c->cfac[axis][par],
                                       c->cden[axis][par],
-                                      axis == 0 ? !c->p.wall_x : !c->p.wall_y};
+                                      axis == 0 ? !c->p.wall_x : !c->p.wall_y, K,
+                                      n >= 2 ? h[K] : 0.0, n >= 2 ? h[n + K] : 0.0};
     }
   return A;
 }
@@ -283,12 +286,23 @@ template <typename T, int N>
 void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, const T* uy,
                     T* po, T* uxo, T* uyo) {
   const CompactArgs<T> A = compact_args<T>(c);
-  T* d = (T*)c->cscratch;
-  T* fx = d + 3 * c->ps;
-  T* fy = d + 6 * c->ps;
-  k_compact_x<T, N><<<(3 * c->p.ny + 63) / 64, 64, 0, c->stream>>>(K, A, p, ux, uy, d, fx);
-  k_compact_y<T, N><<<(3 * c->p.nx + 63) / 64, 64, 0, c->stream>>>(K, A, p, ux, uy, d, fx, fy,
-                                                                   po, uxo, uyo);
+  const int nx = c->p.nx, ny = c->p.ny;
+  const long long ps = c->ps;
+  T* scr = (T*)c->cscratch;  // d, then y, of the y-lines (three fields)
+  T* fx = scr + 3 * ps;      // F_x of the three fields
+  double* fctx = c->cfct;
+  hipStream_t st = c->stream;
+  // chunk length per thread of the x-line solve: the power of two >= nx / 256
+  constexpr int NWV = 4;
+  int lg = 0;
+  while ((64 * NWV << lg) < nx) ++lg;
+  const size_t shx = ((size_t)nx + ((size_t)nx >> lg) + 1) * sizeof(T);
+  k_cline<T, N, NWV><<<3 * ny, 64 * NWV, shx, st>>>(A, A.line[0][0], A.line[0][1], p, ux, uy, fx,
+                                                    fx + ps, fx + 2 * ps, fctx, nx, ny,
+                                                    c->p.wall_x, lg);
+  constexpr int NW = 16;
+  k_cline_y<T, N, NW><<<dim3((nx + 63) / 64, 3), 64 * NW, 0, st>>>(K, A, p, ux, uy, fx, scr,
+                                                                  fctx, po, uxo, uyo);
 }
 
 template <typename T>

@@ -42,7 +42,8 @@ def test_workspace_and_validation():
     bad = [dict(ok, nx=15), dict(ok, rho2=0.0), dict(ok, tau_f=0.5), dict(ok, filter_n=6),
            dict(ok, K=0), dict(ok, K=9), dict(ok, filter_a=1.5), dict(ok, W=0.0),
            dict(ok, eps=-1.0), dict(ok, mu1=-1.0), dict(ok, compact=True, compact_n=6),
-           dict(ok, compact=True, compact_alpha=0.5), dict(ok, compact=True, compact_n=0)]
+           dict(ok, compact=True, compact_alpha=0.5), dict(ok, compact=True, compact_n=0),
+           dict(ok, compact=True, nx=7681)]
     for b in bad:
         with pytest.raises(B.LBMError, match="invalid argument"):
             B.lbm2p_workspace_bytes(B.make_params(b, 0))

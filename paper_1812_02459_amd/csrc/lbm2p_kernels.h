@@ -72,23 +72,37 @@ __device__ __forceinline__ void tile_of(int tiles_x, int& tx, int& ty) {
 
 // Load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS.  Each
 // thread first issues all of its global loads (independent, so their latencies
-// overlap), then writes them to LDS.  Node indices fit in 32 bits (checked at
-// context creation).
+// overlap), then writes them to LDS.  A window inside the lattice (most tiles)
+// takes plain row addresses; only windows that cross an edge map each index
+// through the wrap or mirror.  Node indices fit in 32 bits (checked at context
+// creation).
 template <typename T, typename S, int NT, int RW, int RH>
 __device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, int gx0, int gy0,
                                             const KParams<T>& P, bool odd) {
   constexpr int N = RW * RH, IT = (N + NT - 1) / NT;
   T v[IT];
+  if (gx0 >= 0 && gx0 + RW <= P.nx && gy0 >= 0 && gy0 + RH <= P.ny) {
+    const S* __restrict__ base = src + (gy0 * P.nx + gx0);
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int idx = (int)threadIdx.x + k * NT;
-    if (idx < N) {
-      const int ly = idx / RW, lx = idx - ly * RW;
-      int flip = 0;
-      const int x = map_idx(gx0 + lx, P.nx, P.wx, flip);
-      const int y = map_idx(gy0 + ly, P.ny, P.wy, flip);
-      const T w = T(src[y * P.nx + x]);
-      v[k] = (odd && flip) ? -w : w;
+    for (int k = 0; k < IT; ++k) {
+      const int idx = (int)threadIdx.x + k * NT;
+      if (idx < N) {
+        const int ly = idx / RW, lx = idx - ly * RW;
+        v[k] = T(base[ly * P.nx + lx]);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {
+      const int idx = (int)threadIdx.x + k * NT;
+      if (idx < N) {
+        const int ly = idx / RW, lx = idx - ly * RW;
+        int flip = 0;
+        const int x = map_idx(gx0 + lx, P.nx, P.wx, flip);
+        const int y = map_idx(gy0 + ly, P.ny, P.wy, flip);
+        const T w = T(src[y * P.nx + x]);
+        v[k] = (odd && flip) ? -w : w;
+      }
     }
   }
 #pragma unroll
@@ -153,7 +167,7 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   T sg = g[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) sg = sg + g[i];
-  praw[id] = sg / T(3);
+  praw[id] = divk<3>(sg);
   T ax = g[1];
   ax = ax - g[3];
   ax = ax + g[5];
@@ -203,8 +217,8 @@ __global__ __launch_bounds__(256) void k_fd(KParams<T> P, int tiles_x, const T* 
     const T My = d4<T>(tM(lx, ly - 2), tM(lx, ly - 1), tM(lx, ly + 1), tM(lx, ly + 2));
     const T ph = tP(lx, ly);
     const T mag = sqrt((Gx * Gx + Gy * Gy) + P.eps2);
-    const T nx = Gx / mag, ny = Gy / mag;
-    const T cW = (T(2) * (T(1) - ph * ph)) / P.W;
+    const T nx = qdiv(Gx, mag), ny = qdiv(Gy, mag);
+    const T cW = qdiv(T(2) * (T(1) - ph * ph), P.W);
     const T Jpx = (mag - cW) * nx, Jpy = (mag - cW) * ny;
     const T s = Mx * nx + My * ny;
     const T qx = (P.negM * s) * nx, qy = (P.negM * s) * ny;
@@ -226,7 +240,7 @@ __global__ __launch_bounds__(256) void k_fd(KParams<T> P, int tiles_x, const T* 
     } else if (STAGE == 2) {
       r = T(0.75) * phibar[id] + T(0.25) * (pin + L);
     } else {
-      r = phibar[id] / T(3) + (T(2) * (pin + L)) / T(3);
+      r = divk<3>(phibar[id]) + divk<3>(T(2) * (pin + L));
     }
     out[id] = r;
   }
@@ -359,8 +373,8 @@ __global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T*
       T Fx, Fy, rho, nu, a, b, c, d;
       node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, praw[id], lx, ly, P, Fx, Fy, rho, nu, a, b,
                     c, d);
-      const T vx = jx[id] + Fx / (T(2) * rho);
-      const T vy = jy[id] + Fy / (T(2) * rho);
+      const T vx = jx[id] + qdiv(Fx, T(2) * rho);
+      const T vy = jy[id] + qdiv(Fy, T(2) * rho);
       if (g == 0) {
         uxo[id] = vx;
         uyo[id] = vy;
@@ -484,8 +498,8 @@ __global__ __launch_bounds__(256) void k_vel2(KParams<T> P, int tiles_x, const T
                  (rho - P.rho_ref) * P.gx;
     const T Fy = ((cFy[r] + nu * (Sxy * grx + Syy * gry)) + (cJx[r] * duyx + cJy[r] * duyy)) +
                  (rho - P.rho_ref) * P.gy;
-    sU1x[idx] = cjx[r] + Fx / (T(2) * rho);
-    sU1y[idx] = cjy[r] + Fy / (T(2) * rho);
+    sU1x[idx] = cjx[r] + qdiv(Fx, T(2) * rho);
+    sU1y[idx] = cjy[r] + qdiv(Fy, T(2) * rho);
   }
   __syncthreads();
   if (P.wx || P.wy) {
@@ -530,8 +544,8 @@ __global__ __launch_bounds__(256) void k_vel2(KParams<T> P, int tiles_x, const T
     const T Fy = ((cFy[r] + cnu[r] * (Sxy * cgx[r] + Syy * cgy[r])) +
                   (cJx[r] * duyx + cJy[r] * duyy)) + (crho[r] - P.rho_ref) * P.gy;
     const int id = y * P.nx + x;
-    uxo[id] = cjx[r] + Fx / (T(2) * crho[r]);
-    uyo[id] = cjy[r] + Fy / (T(2) * crho[r]);
+    uxo[id] = cjx[r] + qdiv(Fx, T(2) * crho[r]);
+    uyo[id] = cjy[r] + qdiv(Fy, T(2) * crho[r]);
   }
 }
 
@@ -642,7 +656,7 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, int tiles_x, T* _
       node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, lx, ly, P, Fx, Fy, rho, nu, a, b, c, d);
       T dpx, dpy;
       iso_grad<T>(tPt, lx, ly, dpx, dpy);
-      const T Frx = Fx / rho, Fry = Fy / rho;
+      const T Frx = qdiv(Fx, rho), Fry = qdiv(Fy, rho);
       const T bx = Frx - dpx, by = Fry - dpy;
       T g[9], geq[9], G[9], s[9];
 #pragma unroll
@@ -650,7 +664,7 @@ __global__ __launch_bounds__(256) void k_collide(KParams<T> P, int tiles_x, T* _
       g_eq<T>(p, u_x, u_y, geq);
       src_g<T>(Frx, Fry, u_x, u_y, bx, by, G);
       const T tau_g = nu * T(3) + T(0.5);
-      const T sv = T(1) / tau_g;
+      const T sv = qdiv(T(1), tau_g);
 #pragma unroll
       for (int k = 0; k < 9; ++k) s[k] = P.s_g[k];
       s[7] = sv;

@@ -76,16 +76,21 @@ def parse():
     ap.add_argument("--cpu-side", type=int, default=1024, help="CPU sample window side")
     ap.add_argument("--cpu-steps", type=int, default=120)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the compact-filter and CH-only throughput legs")
     ap.add_argument("--adj-steps", type=int, default=640, help="steps of the adjoint timing")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost (prints its JSON object), e.g. for a kernel trace")
     return ap.parse_args()
 
 
-def run_precision(wl, precision, steps, warmup):
+def run_precision(wl, precision, steps, warmup, params=None):
+    """Time `steps` steps after `warmup` untimed ones, then the average launch time
+    of each pass of the step (10 more steps per pass, outside the timed region)."""
     import torch
     from paper_1812_02459_amd.binding import Sim
-    sim = Sim(wl.params, precision=precision)
+    params = params or wl.params
+    sim = Sim(params, precision=precision)
     sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
     torch.cuda.synchronize()
     sim.step(warmup)
@@ -100,7 +105,16 @@ def run_precision(wl, precision, steps, warmup):
     coll_ms, coll_n = sim.profile_read()
     sim.profile(None)
     diag = sim.volume()
-    nodes = wl.params["nx"] * wl.params["ny"]
+    passes = {}
+    for name in ("gather", "fd", "vel", "filter", "collide"):
+        sim.profile(name)
+        sim.step(10)
+        torch.cuda.synchronize()
+        ms, n = sim.profile_read()
+        if n:
+            passes[name] = round(ms / n, 4)
+    sim.profile(None)
+    nodes = params["nx"] * params["ny"]
     dt = (t1 - t0) / steps
     esz = 4 if precision else 8
     avg_coll = coll_ms / max(coll_n, 1) * 1e-3
@@ -112,7 +126,8 @@ def run_precision(wl, precision, steps, warmup):
         collide_launches=coll_n,
         collide_gbps=coll_bytes / avg_coll / 1e9,
         collide_bytes=coll_bytes,
-        step_gbps_model=step_values(wl.params["K"]) * esz * nodes / dt / 1e9,
+        step_gbps_model=step_values(params["K"]) * esz * nodes / dt / 1e9,
+        pass_ms=passes,
         finite=bool(diag["finite"]),
         sum_phi_drift=diag["sum_phi"] - diag0["sum_phi"],
         max_u=diag["max_u"],
@@ -122,6 +137,31 @@ def run_precision(wl, precision, steps, warmup):
     del sim
     torch.cuda.empty_cache()
     return res
+
+
+def variant_legs(wl, steps, warmup, fp64=True):
+    """The step's other configurations, not the headline: the compact-filter
+    variant on the same bubble workload, and the CH-only step (prescribed
+    single-vortex velocity, no velocity or filter passes) on the same lattice
+    and on 128^2."""
+    from paper_1812_02459_amd import inputs as I
+    keep = ("mlups", "ms_per_step", "pass_ms", "finite")
+    precs = (1, 0) if fp64 else (1,)
+    out = {}
+    pc = dict(wl.params)
+    pc["compact"] = True
+    out["compact_filter"] = {
+        "workload": "same bubble ensemble, compact tridiagonal filter "
+                    f"(N={pc['compact_n']}, alpha={pc['compact_alpha']}) in place of SF-11",
+        **{("fp32" if pr else "fp64"): {k: v for k, v in run_precision(wl, pr, steps, warmup, pc).items()
+                                        if k in keep} for pr in precs}}
+    for n in (wl.params["nx"], 128):
+        v = I.vortex(n=n)
+        out[f"ch_only_{n}"] = {
+            "workload": f"single vortex {n}x{n}, CH-only (prescribed velocity)",
+            **{("fp32" if pr else "fp64"): {k: val for k, val in run_precision(v, pr, steps, warmup).items()
+                                            if k in keep} for pr in precs}}
+    return out
 
 
 def adjoint_cost(precision, nsteps, k=64, warmup=64):
@@ -242,6 +282,12 @@ def main():
         print(f"# adjoint/forward: fp32 {adj['fp32']['ratio']:.2f}"
               + (f", fp64 {adj['fp64']['ratio']:.2f}" if "fp64" in adj else ""),
               file=sys.stderr, flush=True)
+    variants = None
+    if not args.no_variants:
+        variants = variant_legs(wl, min(args.steps, 300), min(args.warmup, 20), not args.no_fp64)
+        print("# variants: " + ", ".join(
+            f"{k} fp32 {v['fp32']['mlups']:.0f} MLUPS" for k, v in variants.items()),
+            file=sys.stderr, flush=True)
     copy_gbps = copy_bandwidth()
     cpu = None
     if not args.no_cpu:
@@ -285,16 +331,17 @@ def main():
             "avg_launch_ms": round(r32["collide_ms"], 4),
         },
         "step": {
-            "fp32": {k: r32[k] for k in ("mlups", "ms_per_step", "step_gbps_model", "finite",
-                                          "sum_phi_drift", "max_u", "phi_range")},
+            "fp32": {k: r32[k] for k in ("mlups", "ms_per_step", "step_gbps_model", "pass_ms",
+                                          "finite", "sum_phi_drift", "max_u", "phi_range")},
         },
         "adjoint": adj,
+        "variants": variants,
         "copy_GBps": round(copy_gbps, 1),
         "cpu_baseline": cpu,
     }
     if r64 is not None:
         out["step"]["fp64"] = {k: r64[k] for k in ("mlups", "ms_per_step", "step_gbps_model",
-                                                    "finite", "sum_phi_drift", "max_u",
+                                                    "pass_ms", "finite", "sum_phi_drift", "max_u",
                                                     "phi_range", "collide_ms", "collide_gbps")}
         out["step"]["fp64"]["collide_frac"] = round(r64["collide_gbps"] / HBM_PEAK_GBPS, 4)
     print(json.dumps(out), flush=True)

@@ -133,6 +133,11 @@ __device__ __forceinline__ T block_carry(Aff<T> m, T* sWa, T* sWb) {
   return ea * c + eb;
 }
 
+// Columns per workgroup of the y-line solve (16, 32 or 64); compile-time tuning.
+#ifndef LBM2P_CLINE_Y_CW
+#define LBM2P_CLINE_Y_CW 16
+#endif
+
 // Longest line the LDS-staged line solve takes (the FP64 line, padded, in 64 KB).
 constexpr int COMPACT_MAX_N = 7680;
 
@@ -221,13 +226,15 @@ __global__ __launch_bounds__(64 * NWV) void k_cline(CompactArgs<T> A, CompactLin
   }
 }
 
-// y-lines and the update.  Lanes are 64 adjacent columns (coalesced rows);
-// the NW waves of a workgroup split each column into NW chunks, exchange their
-// chunks' affine maps through LDS, and replay.  The right-hand side comes from
-// a sliding window of 2N+1 values per column; d and y go through a scratch
+// y-lines and the update.  A workgroup takes CW adjacent columns: lane l of a
+// wave works on column l mod CW and chunk slot l / CW, so a wave's loads are
+// 64 / CW row segments of CW consecutive values, and the NW waves together
+// split each column into NW * 64 / CW chunks.  The chunks exchange their
+// affine maps through LDS, then replay.  The right-hand side comes from a
+// sliding window of 2N+1 values per column; d and y go through a scratch
 // plane.  The last pass forms chi~ = chi - a [(chi - F_x) + (chi - F_y)] with
 // both directions' Sherman-Morrison corrections.  grid = (column blocks, 3).
-template <typename T, int N, int NW>
+template <typename T, int N, int NW, int CW>
 __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T> A,
                                                      const T* __restrict__ c0,
                                                      const T* __restrict__ c1,
@@ -236,8 +243,10 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
                                                      const double* __restrict__ fctx,
                                                      T* __restrict__ o0, T* __restrict__ o1,
                                                      T* __restrict__ o2) {
-  __shared__ T sA[NW][64], sB[NW][64];
-  __shared__ T sY0[64], sYl[64];
+  static_assert(CW == 16 || CW == 32 || CW == 64, "column block of 16, 32 or 64");
+  constexpr int S = 64 / CW, NCH = NW * S;
+  __shared__ T sA[NCH][CW], sB[NCH][CW];
+  __shared__ T sY0[CW], sYl[CW];
   const int f = (int)blockIdx.y;
   const bool odd = f != 0;
   const T* src = f == 0 ? c0 : f == 1 ? c1 : c2;
@@ -248,12 +257,13 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
   const CompactLine Lx = odd ? A.line[0][1] : A.line[0][0];
   const int nx = P.nx, n = P.ny;
   const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
-  const int x = (int)blockIdx.x * 64 + lane;
+  const int col = lane % CW, q = w * S + lane / CW;   // column in the block, chunk
+  const int x = (int)blockIdx.x * CW + col;
   const bool live = x < nx;
   // idle lanes (beyond the last column) read a real column and write nothing
   const int xs = live ? x : nx - 1;
-  const int m = (n + NW - 1) / NW;
-  const int i0 = w * m < n ? w * m : n, i1 = (w + 1) * m < n ? (w + 1) * m : n;
+  const int m = (n + NCH - 1) / NCH;
+  const int i0 = q * m < n ? q * m : n, i1 = (q + 1) * m < n ? (q + 1) * m : n;
   T ah[N + 1];
 #pragma unroll
   for (int k = 0; k <= N; ++k) ah[k] = T(A.a[k] / 2.0);
@@ -291,11 +301,11 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
       }
     }
   }
-  sA[w][lane] = M.a;
-  sB[w][lane] = M.b;
+  sA[q][col] = M.a;
+  sB[q][col] = M.b;
   __syncthreads();
   T d = T(0);
-  for (int k = 0; k < w; ++k) d = sA[k][lane] * d + sB[k][lane];
+  for (int k = 0; k < q; ++k) d = sA[k][col] * d + sB[k][col];
   __syncthreads();
   if (i0 < i1) load_win(i0);
   for (int base = i0; base < i1; base += CB) {
@@ -324,11 +334,11 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
     for (int j = 0; j < CB; ++j)
       if (top - j >= i0) Mb = aff_after(Aff<T>{-cl_cp<T>(L, top - j, n), v[j]}, Mb);
   }
-  sA[w][lane] = Mb.a;
-  sB[w][lane] = Mb.b;
+  sA[q][col] = Mb.a;
+  sB[q][col] = Mb.b;
   __syncthreads();
   T y = T(0);
-  for (int k = NW - 1; k > w; --k) y = sA[k][lane] * y + sB[k][lane];
+  for (int k = NCH - 1; k > q; --k) y = sA[k][col] * y + sB[k][col];
   for (int top = i1 - 1; top >= i0; top -= CB) {
     T v[CB];
 #pragma unroll
@@ -340,13 +350,13 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
         const int i = top - j;
         y = v[j] - cl_cp<T>(L, i, n) * y;
         if (live) sc[(long long)i * nx + xs] = y;
-        if (i == n - 1) sYl[lane] = y;
-        if (i == 0) sY0[lane] = y;
+        if (i == n - 1) sYl[col] = y;
+        if (i == 0) sY0[col] = y;
       }
   }
   __syncthreads();
   T fct = T(0);
-  if (L.cyclic) fct = (sY0[lane] + T(L.fac) * sYl[lane]) / T(L.den);
+  if (L.cyclic) fct = (sY0[col] + T(L.fac) * sYl[col]) / T(L.den);
   if (!live) return;
   const T a = P.fa;
   for (int i = i0; i < i1; ++i) {

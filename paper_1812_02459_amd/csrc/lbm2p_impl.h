@@ -300,9 +300,10 @@ void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, 
   k_cline<T, N, NWV><<<3 * ny, 64 * NWV, shx, st>>>(A, A.line[0][0], A.line[0][1], p, ux, uy, fx,
                                                     fx + ps, fx + 2 * ps, fctx, nx, ny,
                                                     c->p.wall_x, lg);
-  constexpr int NW = 16;
-  k_cline_y<T, N, NW><<<dim3((nx + 63) / 64, 3), 64 * NW, 0, st>>>(K, A, p, ux, uy, fx, scr,
-                                                                  fctx, po, uxo, uyo);
+  // y-lines: 16 waves per workgroup, CW columns per workgroup
+  constexpr int NW = 16, CW = LBM2P_CLINE_Y_CW;
+  k_cline_y<T, N, NW, CW><<<dim3((nx + CW - 1) / CW, 3), 64 * NW, 0, st>>>(
+      K, A, p, ux, uy, fx, scr, fctx, po, uxo, uyo);
 }
 
 template <typename T>
@@ -346,18 +347,19 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
     if (p.original_ch) {
       k_copy<T><<<blocks1d(n), 256, 0, st>>>(phibar, phi, n);
     } else {
-      const Tiles<FD_TX, FD_TY> tl(p);
+      using C = StepCfg<T>;
+      const Tiles<C::TX, C::FD_TY> tl(p);
       {
         ProfScope ps(c, PASS_FD);
-        k_fd<T, 1, FD_TX, FD_TY><<<tl.grid(), 256, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
+        k_fd<T, 1, C::TX, C::FD_TY, C::FD_NT><<<tl.grid(), C::FD_NT, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
       }
       {
         ProfScope ps(c, PASS_FD);
-        k_fd<T, 2, FD_TX, FD_TY><<<tl.grid(), 256, 0, st>>>(K, tl.tx, phi1, phibar, phi2);
+        k_fd<T, 2, C::TX, C::FD_TY, C::FD_NT><<<tl.grid(), C::FD_NT, 0, st>>>(K, tl.tx, phi1, phibar, phi2);
       }
       {
         ProfScope ps(c, PASS_FD);
-        k_fd<T, 3, FD_TX, FD_TY><<<tl.grid(), 256, 0, st>>>(K, tl.tx, phi2, phibar, phi);
+        k_fd<T, 3, C::TX, C::FD_TY, C::FD_NT><<<tl.grid(), C::FD_NT, 0, st>>>(K, tl.tx, phi2, phibar, phi);
       }
     }
     if (p.coupled) {
@@ -367,7 +369,8 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       T* uny = (T*)c->U[1 - c->uo][1];
       const T* ux = uox;
       const T* uy = uoy;
-      const Tiles<VEL_TX, VEL_TY> tv(p);
+      using C = StepCfg<T>;
+      const Tiles<C::TX, C::VEL_TY> tv(p);
       int done = 0, launch = 0;
       while (done < p.K) {
         // two sweeps per launch, one for an odd remainder; when recording for
@@ -377,15 +380,18 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         ProfScope ps(c, PASS_VEL);
         // (FP64: one sweep per launch -- the two-sweep kernel's LDS footprint
         // costs more occupancy than its saved traffic is worth in double)
-        if (sizeof(T) == 4 && p.K - done >= 2 && !c->rec) {
-          k_vel2<T, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(
-              K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
-          done += 2;
-        } else {
-          k_vel<T, 1, VEL_TX, VEL_TY><<<tv.grid(), 256, 0, st>>>(
-              K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
-          done += 1;
+        bool two = false;
+        if constexpr (sizeof(T) == 4) {
+          if (p.K - done >= 2 && !c->rec) {
+            k_vel2<T, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
+                K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
+            two = true;
+          }
         }
+        if (!two)
+          k_vel<T, 1, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
+              K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
+        done += two ? 2 : 1;
         ux = ox;
         uy = oy;
         ++launch;
@@ -407,24 +413,24 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         k_copy<T><<<blocks1d(n), 256, 0, st>>>(uy, uny, n);
       } else {
         ProfScope ps(c, PASS_FILTER);
-        const Tiles<FIL_TX, FIL_TY> tf(p);
+        const Tiles<C::TX, C::FIL_TY> tf(p);
         const T* pr = (const T*)c->praw;
         T* po = (T*)c->pt;
         switch (c->fn) {
-          case 2: k_filter<T, 2, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-          case 3: k_filter<T, 3, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-          case 4: k_filter<T, 4, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-          default: k_filter<T, 5, FIL_TX, FIL_TY><<<tf.grid(), 256, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+          case 2: k_filter<T, 2, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+          case 3: k_filter<T, 3, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+          case 4: k_filter<T, 4, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+          default: k_filter<T, 5, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
         }
       }
       {
         ProfScope ps(c, PASS_COLLIDE);
-        const Tiles<COL_TX, COL_TY> tc(p);
+        const Tiles<C::TX, C::COL_TY> tc(p);
         if (par == 0)
-          k_collide<T, 0, true, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
+          k_collide<T, 0, true, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
               K, tc.tx, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
         else
-          k_collide<T, 1, true, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
+          k_collide<T, 1, true, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
               K, tc.tx, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
       }
       c->uo = 1 - c->uo;
@@ -432,12 +438,13 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       T* ux = (T*)c->U[0][0];
       T* uy = (T*)c->U[0][1];
       ProfScope ps(c, PASS_COLLIDE);
-      const Tiles<COL_TX, COL_TY> tc(p);
+      using C = StepCfg<T>;
+      const Tiles<C::TX, C::COL_TY> tc(p);
       if (par == 0)
-        k_collide<T, 0, false, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
+        k_collide<T, 0, false, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
             K, tc.tx, Af, Ag, phi, nullptr, ux, uy, ux, uy);
       else
-        k_collide<T, 1, false, COL_TX, COL_TY><<<tc.grid(), 256, 0, st>>>(
+        k_collide<T, 1, false, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
             K, tc.tx, Af, Ag, phi, nullptr, ux, uy, ux, uy);
     }
     c->parity ^= 1;

@@ -16,11 +16,34 @@
 
 namespace lbm2p {
 
-// tile shapes of the step's kernels (nodes per workgroup of 256 threads)
+// Tile shapes of the adjoint's kernels (nodes per workgroup)
 constexpr int FD_TX = 64, FD_TY = 16;
 constexpr int VEL_TX = 64, VEL_TY = 8;
 constexpr int FIL_TX = 64, FIL_TY = 16;
 constexpr int COL_TX = 64, COL_TY = 8;
+
+// Tile shapes of the forward step's kernels per precision: 64 nodes wide (one
+// wavefront per tile row), TY rows, NT threads per workgroup.  Taller tiles
+// recompute fewer halo nodes but hold more LDS per workgroup.  Compile-time
+// tuning parameters.
+#ifndef LBM2P_F32_TILES
+#define LBM2P_F32_TILES 32, 512, 16, 512, 32, 512, 16, 256
+#endif
+#ifndef LBM2P_F64_TILES
+#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256
+#endif
+template <int FD_Y, int FD_T, int VEL_Y, int VEL_T, int FIL_Y, int FIL_T, int COL_Y, int COL_T>
+struct StepTiles {
+  static constexpr int TX = 64;
+  static constexpr int FD_TY = FD_Y, FD_NT = FD_T, VEL_TY = VEL_Y, VEL_NT = VEL_T;
+  static constexpr int FIL_TY = FIL_Y, FIL_NT = FIL_T, COL_TY = COL_Y, COL_NT = COL_T;
+};
+template <typename T>
+struct StepCfg;
+template <>
+struct StepCfg<float> : StepTiles<LBM2P_F32_TILES> {};
+template <>
+struct StepCfg<double> : StepTiles<LBM2P_F64_TILES> {};
 
 template <typename T>
 struct KParams {
@@ -187,10 +210,9 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
 // ------------------------------------------------- a2: FD sub-step stage
 // L(phi*) = div_4 (lambda J_phi + q)  (eq:final_mCHE, eq:fourOrder_FDM) and the
 // TVD-RK3 combination of eq:TVD-3order for STAGE 1, 2, 3.
-template <typename T, int STAGE, int TX, int TY>
-__global__ __launch_bounds__(256) void k_fd(KParams<T> P, int tiles_x, const T* __restrict__ in,
+template <typename T, int STAGE, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* __restrict__ in,
                                             const T* __restrict__ phibar, T* __restrict__ out) {
-  constexpr int NT = 256;
   constexpr int W5 = TX + 10, H5 = TY + 10;   // phi*, halo 5
   constexpr int W4 = TX + 8, H4 = TY + 8;     // mu*, halo 4
   constexpr int W2 = TX + 4, H2 = TY + 4;     // J_d, halo 2
@@ -320,13 +342,12 @@ __device__ __forceinline__ void node_force(const Tile<T>& tP, const Tile<T>& tPx
 // sweep k is evaluated on the tile grown by KS-1-k nodes, so the next sweep
 // finds its halo in LDS.  Every sweep computes exactly what a one-sweep launch
 // computes at the same node.
-template <typename T, int KS, int TX, int TY>
-__global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T* __restrict__ phi,
+template <typename T, int KS, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                              const T* __restrict__ praw, const T* __restrict__ jx,
                                              const T* __restrict__ jy, const T* __restrict__ uxi,
                                              const T* __restrict__ uyi, T* __restrict__ uxo,
                                              T* __restrict__ uyo) {
-  constexpr int NT = 256;
   constexpr int HP = KS + 1;                      // phi halo
   constexpr int WP = TX + 2 * HP, HPH = TY + 2 * HP;
   constexpr int WD = TX + 2 * KS, HD = TY + 2 * KS;  // derived fields and u^0
@@ -415,21 +436,24 @@ __global__ __launch_bounds__(256) void k_vel(KParams<T> P, int tiles_x, const T*
 
 // Two velocity sweeps in one launch, for the FP32 step.  phi and p are fixed
 // during the sweeps, so F_p + F_s, J = c_J grad mu, grad rho, nu and rho are the
-// same in both: they are evaluated once per node of the tile grown by one and
-// kept in registers; the second sweep re-evaluates only the u-dependent F_nu and
-// F_m (F summed in the order (((F_p + F_s) + F_nu) + F_m) + F_g as in
-// node_force).  Each thread owns the same nodes in both sweeps.
-template <typename T, int TX, int TY>
-__global__ __launch_bounds__(256) void k_vel2(KParams<T> P, int tiles_x, const T* __restrict__ phi,
+// same in both: on the tile's own nodes they are evaluated once and kept in
+// registers (each thread owns TX*TY/NT nodes in both sweeps), and the second
+// sweep re-evaluates only the u-dependent F_nu and F_m (F summed in the order
+// (((F_p + F_s) + F_nu) + F_m) + F_g as in node_force).  The first sweep also
+// covers the ring of nodes around the tile, which the second sweep's stencils
+// read.
+template <typename T, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                               const T* __restrict__ praw, const T* __restrict__ jx,
                                               const T* __restrict__ jy, const T* __restrict__ uxi,
                                               const T* __restrict__ uyi, T* __restrict__ uxo,
                                               T* __restrict__ uyo) {
-  constexpr int NT = 256;
+  static_assert((TX * TY) % NT == 0, "whole tile rows per thread group");
   constexpr int WP = TX + 6, HPH = TY + 6;   // phi, halo 3
   constexpr int WD = TX + 4, HD = TY + 4;    // derived fields and u^0, halo 2
   constexpr int W1 = TX + 2, H1 = TY + 2;    // first sweep and u^1, halo 1
-  constexpr int NR = (W1 * H1 + NT - 1) / NT;
+  constexpr int NI = TX * TY / NT;           // tile nodes per thread
+  constexpr int NRING = 2 * W1 + 2 * TY;     // nodes of the halo-1 ring
   __shared__ T sP[WP * HPH];
   __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
   __shared__ T sU0x[WD * HD], sU0y[WD * HD], sU1x[W1 * H1], sU1y[W1 * H1];
@@ -453,53 +477,84 @@ __global__ __launch_bounds__(256) void k_vel2(KParams<T> P, int tiles_x, const T
   __syncthreads();
   const Tile<T> tPx{sPx, WD, 2}, tPy{sPy, WD, 2}, tMu{sMu, WD, 2}, tRho{sRho, WD, 2},
       tU0x{sU0x, WD, 2}, tU0y{sU0y, WD, 2}, tU1x{sU1x, W1, 1}, tU1y{sU1y, W1, 1};
-  // per owned node: F_p + F_s (2), J (2), grad rho (2), nu, rho, j (2)
-  T cFx[NR], cFy[NR], cJx[NR], cJy[NR], cgx[NR], cgy[NR], cnu[NR], crho[NR], cjx[NR], cjy[NR];
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const int idx = threadIdx.x + r * NT;
-    if (idx >= W1 * H1) continue;
-    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+  // the tile grown by one lies inside the lattice: plain row addresses
+  const bool inner = x0 >= 1 && x0 + W1 - 1 <= P.nx && y0 >= 1 && y0 + H1 - 1 <= P.ny;
+  auto node_id = [&](int lx, int ly) {
     const int gxn = x0 + lx, gyn = y0 + ly;
-    // ghosts beyond a wall are filled below from their mirror node
-    if ((P.wx && (gxn < 0 || gxn >= P.nx)) || (P.wy && (gyn < 0 || gyn >= P.ny))) continue;
+    if (inner) return gyn * P.nx + gxn;
+    // wrap or mirror (a ghost beyond a wall reads its mirror node; its u^1 is
+    // replaced below)
     int flip = 0;
     const int x = map_idx(gxn, P.nx, P.wx, flip);
     const int y = map_idx(gyn, P.ny, P.wy, flip);
-    const int id = y * P.nx + x;
+    return y * P.nx + x;
+  };
+  // u-independent force parts at (lx, ly), then the first sweep's u^1 there
+  struct Parts {
+    T Fx, Fy, Jx, Jy, gx, gy, nu, rho, jx, jy;
+  };
+  auto parts = [&](int lx, int ly) {
+    const int id = node_id(lx, ly);
+    Parts q;
     const T p = praw[id];
-    cjx[r] = jx[id];
-    cjy[r] = jy[id];
+    q.jx = jx[id];
+    q.jy = jy[id];
     const T ph = tP(lx, ly);
-    const T rho = density<T>(ph, P.rho1, P.rho2);
-    const T nu = kin_visc<T>(ph, rho, P.mu1, P.mu2);
+    q.rho = density<T>(ph, P.rho1, P.rho2);
+    q.nu = kin_visc<T>(ph, q.rho, P.mu1, P.mu2);
     T dmx, dmy;
     iso_grad<T>(tMu, lx, ly, dmx, dmy);
     const T dxyy = iso_grad_x<T>(ProdYY<T>{tPy}, lx, ly);
     T dxxy, dyxy;
     iso_grad<T>(ProdXY<T>{tPx, tPy}, lx, ly, dxxy, dyxy);
     const T dyxx = iso_grad_y<T>(ProdXX<T>{tPx}, lx, ly);
-    T grx, gry;
-    iso_grad<T>(tRho, lx, ly, grx, gry);
-    cFx[r] = (-p) * grx + P.kappa * (dxyy - dyxy);
-    cFy[r] = (-p) * gry + P.kappa * (dyxx - dxxy);
-    cJx[r] = P.cJ * dmx;
-    cJy[r] = P.cJ * dmy;
-    cgx[r] = grx;
-    cgy[r] = gry;
-    cnu[r] = nu;
-    crho[r] = rho;
-    // first sweep from u^0
+    iso_grad<T>(tRho, lx, ly, q.gx, q.gy);
+    q.Fx = (-p) * q.gx + P.kappa * (dxyy - dyxy);
+    q.Fy = (-p) * q.gy + P.kappa * (dyxx - dxxy);
+    q.Jx = P.cJ * dmx;
+    q.Jy = P.cJ * dmy;
+    return q;
+  };
+  auto sweep = [&](const Parts& q, const Tile<T>& tUx, const Tile<T>& tUy, int lx, int ly,
+                   T& vx, T& vy) {
     T duxx, duxy, duyx, duyy;
-    iso_grad<T>(tU0x, lx, ly, duxx, duxy);
-    iso_grad<T>(tU0y, lx, ly, duyx, duyy);
+    iso_grad<T>(tUx, lx, ly, duxx, duxy);
+    iso_grad<T>(tUy, lx, ly, duyx, duyy);
     const T Sxx = duxx + duxx, Sxy = duyx + duxy, Syy = duyy + duyy;
-    const T Fx = ((cFx[r] + nu * (Sxx * grx + Sxy * gry)) + (cJx[r] * duxx + cJy[r] * duxy)) +
-                 (rho - P.rho_ref) * P.gx;
-    const T Fy = ((cFy[r] + nu * (Sxy * grx + Syy * gry)) + (cJx[r] * duyx + cJy[r] * duyy)) +
-                 (rho - P.rho_ref) * P.gy;
-    sU1x[idx] = cjx[r] + qdiv(Fx, T(2) * rho);
-    sU1y[idx] = cjy[r] + qdiv(Fy, T(2) * rho);
+    const T Fx = ((q.Fx + q.nu * (Sxx * q.gx + Sxy * q.gy)) + (q.Jx * duxx + q.Jy * duxy)) +
+                 (q.rho - P.rho_ref) * P.gx;
+    const T Fy = ((q.Fy + q.nu * (Sxy * q.gx + Syy * q.gy)) + (q.Jx * duyx + q.Jy * duyy)) +
+                 (q.rho - P.rho_ref) * P.gy;
+    vx = q.jx + qdiv(Fx, T(2) * q.rho);
+    vy = q.jy + qdiv(Fy, T(2) * q.rho);
+  };
+  Parts c[NI];
+#pragma unroll
+  for (int r = 0; r < NI; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    const int ly = idx / TX, lx = idx - ly * TX;
+    c[r] = parts(lx, ly);
+    T vx, vy;
+    sweep(c[r], tU0x, tU0y, lx, ly, vx, vy);
+    sU1x[(ly + 1) * W1 + lx + 1] = vx;
+    sU1y[(ly + 1) * W1 + lx + 1] = vy;
+  }
+  // the ring: rows -1 and TY (W1 nodes each), then columns -1 and TX
+  for (int k = threadIdx.x; k < NRING; k += NT) {
+    int lx, ly;
+    if (k < 2 * W1) {
+      ly = k < W1 ? -1 : TY;
+      lx = (k < W1 ? k : k - W1) - 1;
+    } else {
+      const int j = k - 2 * W1;
+      ly = j >> 1;
+      lx = (j & 1) ? TX : -1;
+    }
+    const Parts q = parts(lx, ly);
+    T vx, vy;
+    sweep(q, tU0x, tU0y, lx, ly, vx, vy);
+    sU1x[(ly + 1) * W1 + lx + 1] = vx;
+    sU1y[(ly + 1) * W1 + lx + 1] = vy;
   }
   __syncthreads();
   if (P.wx || P.wy) {
@@ -515,48 +570,39 @@ __global__ __launch_bounds__(256) void k_vel2(KParams<T> P, int tiles_x, const T
       if (P.wy && gyn >= P.ny) { my = 2 * P.ny - 1 - gyn; flips ^= 1; }
       if (mx == gxn && my == gyn) continue;            // not a ghost
       const int lmx = mx - x0, lmy = my - y0;
-      if (lmx < -1 || lmx >= TX + 1 || lmy < -1 || lmy >= TY + 1) {
-        sU1x[idx] = T(0);                              // never read by an in-domain output
-        sU1y[idx] = T(0);
-        continue;
+      T vx = T(0), vy = T(0);                          // never read by an in-domain output
+      if (lmx >= -1 && lmx < TX + 1 && lmy >= -1 && lmy < TY + 1) {
+        const int om = (lmy + 1) * W1 + (lmx + 1);
+        vx = flips ? -sU1x[om] : sU1x[om];
+        vy = flips ? -sU1y[om] : sU1y[om];
       }
-      const int om = (lmy + 1) * W1 + (lmx + 1);
-      sU1x[idx] = flips ? -sU1x[om] : sU1x[om];
-      sU1y[idx] = flips ? -sU1y[om] : sU1y[om];
+      sU1x[idx] = vx;
+      sU1y[idx] = vy;
     }
     __syncthreads();
   }
-  // second sweep from u^1 on the tile
+  // second sweep from u^1 on the tile's own nodes
 #pragma unroll
-  for (int r = 0; r < NR; ++r) {
+  for (int r = 0; r < NI; ++r) {
     const int idx = threadIdx.x + r * NT;
-    if (idx >= W1 * H1) continue;
-    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
-    if (lx < 0 || lx >= TX || ly < 0 || ly >= TY) continue;
+    const int ly = idx / TX, lx = idx - ly * TX;
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) continue;
-    T duxx, duxy, duyx, duyy;
-    iso_grad<T>(tU1x, lx, ly, duxx, duxy);
-    iso_grad<T>(tU1y, lx, ly, duyx, duyy);
-    const T Sxx = duxx + duxx, Sxy = duyx + duxy, Syy = duyy + duyy;
-    const T Fx = ((cFx[r] + cnu[r] * (Sxx * cgx[r] + Sxy * cgy[r])) +
-                  (cJx[r] * duxx + cJy[r] * duxy)) + (crho[r] - P.rho_ref) * P.gx;
-    const T Fy = ((cFy[r] + cnu[r] * (Sxy * cgx[r] + Syy * cgy[r])) +
-                  (cJx[r] * duyx + cJy[r] * duyy)) + (crho[r] - P.rho_ref) * P.gy;
+    T vx, vy;
+    sweep(c[r], tU1x, tU1y, lx, ly, vx, vy);
     const int id = y * P.nx + x;
-    uxo[id] = cjx[r] + qdiv(Fx, T(2) * crho[r]);
-    uyo[id] = cjy[r] + qdiv(Fy, T(2) * crho[r]);
+    uxo[id] = vx;
+    uyo[id] = vy;
   }
 }
 
 // ------------------------------------------------ a4: explicit selective filter
 // chi <- chi - a [ sum_j d_|j| chi(x+j, y) + sum_j d_|j| chi(x, y+j) ]  (eq:filter)
-template <typename T, int N, int TX, int TY>
-__global__ __launch_bounds__(256) void k_filter(KParams<T> P, int tiles_x, const T* __restrict__ pin,
+template <typename T, int N, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_filter(KParams<T> P, int tiles_x, const T* __restrict__ pin,
                                                 const T* __restrict__ uxin,
                                                 const T* __restrict__ uyin, T* __restrict__ pout,
                                                 T* __restrict__ uxout, T* __restrict__ uyout) {
-  constexpr int NT = 256;
   constexpr int WN = TX + 2 * N, HN = TY + 2 * N;
   __shared__ T s0[WN * HN], s1[WN * HN], s2[WN * HN];
   int bx, by;
@@ -595,13 +641,12 @@ __global__ __launch_bounds__(256) void k_filter(KParams<T> P, int tiles_x, const
 // ------------------------------------------------------ a5: collide + stream
 // MRT collision of f (eq:distribution_CH) and g (eq:distribution_NS) at n+1,
 // written to the streaming slots of the other parity.
-template <typename T, int PAR, bool COUPLED, int TX, int TY>
-__global__ __launch_bounds__(256) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
+template <typename T, int PAR, bool COUPLED, int TX, int TY, int NT>
+__global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
                                                  const T* __restrict__ phi, const T* __restrict__ pt,
                                                  const T* __restrict__ ux, const T* __restrict__ uy,
                                                  const T* __restrict__ uox,
                                                  const T* __restrict__ uoy) {
-  constexpr int NT = 256;
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   __shared__ T sP[W2 * H2];
   __shared__ T sPx[COUPLED ? W1 * H1 : 1], sPy[COUPLED ? W1 * H1 : 1], sMu[W1 * H1],

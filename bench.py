@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the compact-filter and CH-only throughput legs")
     ap.add_argument("--adj-steps", type=int, default=640, help="steps of the adjoint timing")
+    ap.add_argument("--variants-only", action="store_true",
+                    help="only the compact-filter and CH-only legs (prints their JSON object)")
     ap.add_argument("--adjoint-only", action="store_true",
                     help="only the adjoint cost (prints its JSON object), e.g. for a kernel trace")
     return ap.parse_args()
@@ -263,6 +265,10 @@ def main():
     t0 = time.perf_counter()
     wl = I.bubble_ensemble(n=args.n, nb=args.bubbles, seed=0, steps=args.steps)
     print(f"# workload built in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    if args.variants_only:
+        print(json.dumps({"variants": variant_legs(wl, args.steps, args.warmup,
+                                                   not args.no_fp64)}), flush=True)
+        return
     r32 = run_precision(wl, 1, args.steps, args.warmup)
     print(f"# fp32: {r32['mlups']:.0f} MLUPS, collide {r32['collide_ms']:.3f} ms "
           f"({r32['collide_gbps']:.0f} GB/s)", file=sys.stderr, flush=True)

@@ -1014,22 +1014,4 @@ __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ part, i
 }
 }  // namespace
 
-// gather m7, m8 of the pre-collision g (the stress moments the g-collision's
-// rate derivative needs), written while a step is recomputed for the adjoint
-template <typename T, int PAR>
-__global__ __launch_bounds__(256) void k_rec_m78(KParams<T> P, const T* __restrict__ Ag,
-                                                 T* __restrict__ m7, T* __restrict__ m8) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  int rd[9];
-  slots<PAR>(P, x, y, rd);
-  T g[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = Ag[rd[i]];
-  m7[id] = ((g[1] - g[2]) + g[3]) - g[4];
-  m8[id] = ((g[5] - g[6]) + g[7]) - g[8];
-}
-
 }  // namespace lbm2p

@@ -13,6 +13,23 @@ namespace {
 // adjoint's passes chain several load / sync / compute phases, and more waves
 // per tile hide their latency on grids of a few 10^5 nodes
 constexpr int ADJ_NT = 512;
+// Tiles (rows of 64 nodes, threads) of the reverse collision and the reverse
+// velocity sweeps per precision (measured on the 256 x 1024 rising bubble: FP32
+// gains from 1024-thread tiles, FP64 loses to register pressure there).
+template <int TY_, int NT_>
+struct AdjTile {
+  static constexpr int TY = TY_, NT = NT_;
+};
+template <typename T>
+struct AdjCfg {
+  using Col = AdjTile<16, 1024>;
+  using Vel = AdjTile<16, 1024>;
+};
+template <>
+struct AdjCfg<double> {
+  using Col = AdjTile<8, 512>;
+  using Vel = AdjTile<8, 512>;
+};
 
 // planes of one recorded step
 template <typename T>
@@ -162,8 +179,9 @@ void launch_adj_collide(lbm2p_ctx* c, const KParams<T>& K, const AdjConst& C,
                         const AdjWork<T>& Wk, const Slot<T>& sl, const T* ux, const T* uy,
                         const T* uox, const T* uoy, const T* Afi, const T* Agi,
                         const Pending<T>& pd, T* Afo, T* Ago, T* Uox, T* Uoy) {
-  const Tiles<COL_TX, COL_TY> tc(c->p);
-  k_adj_collide<T, COUPLED, PEND, COL_TX, COL_TY, ADJ_NT><<<tc.grid(), ADJ_NT, 0, c->stream>>>(
+  using AdjCol = typename AdjCfg<T>::Col;
+  const Tiles<64, AdjCol::TY> tc(c->p);
+  k_adj_collide<T, COUPLED, PEND, 64, AdjCol::TY, AdjCol::NT><<<tc.grid(), AdjCol::NT, 0, c->stream>>>(
       K, C, tc.tx, sl.phi, sl.pt, ux, uy, uox, uoy, sl.m7, sl.m8, Afi, Agi, pd.phi, pd.p, pd.jx,
       pd.jy, Afo, Ago, Uox, Uoy, Wk);
 }
@@ -208,16 +226,17 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
     }
     // velocity sweeps last to first; sweep k reads u^k (u^0 = u~^n)
     int cur = 0;
-    const Tiles<VEL_TX, VEL_TY> tv(p);
+    using AdjVel = typename AdjCfg<T>::Vel;
+    const Tiles<64, AdjVel::TY> tv(p);
     for (int k = p.K - 1; k >= 0; --k) {
       const T* ux = k == 0 ? uox : sl.u[k][0];
       const T* uy = k == 0 ? uoy : sl.u[k][1];
       if (k == p.K - 1) {
-        k_adj_vel<T, true, VEL_TX, VEL_TY, ADJ_NT><<<tv.grid(), ADJ_NT, 0, st>>>(K, C, tv.tx, sl.phi, sl.praw,
+        k_adj_vel<T, true, 64, AdjVel::TY, AdjVel::NT><<<tv.grid(), AdjVel::NT, 0, st>>>(K, C, tv.tx, sl.phi, sl.praw,
                                                                       ux, uy, 1, Wk);
         cur = 0;
       } else {
-        k_adj_vel<T, false, VEL_TX, VEL_TY, ADJ_NT><<<tv.grid(), ADJ_NT, 0, st>>>(K, C, tv.tx, sl.phi,
+        k_adj_vel<T, false, 64, AdjVel::TY, AdjVel::NT><<<tv.grid(), AdjVel::NT, 0, st>>>(K, C, tv.tx, sl.phi,
                                                                        sl.praw, ux, uy, cur, Wk);
         cur = 1 - cur;
       }

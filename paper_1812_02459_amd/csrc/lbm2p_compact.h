@@ -196,21 +196,22 @@ __global__ __launch_bounds__(64 * NWV) void k_cline(CompactArgs<T> A, CompactLin
     sd[cpad(e, lg)] = r;
   }
   __syncthreads();
-  // forward sweep: compose, scan, replay (d_i in place of r_i)
+  // forward sweep: compose, scan, replay (d_i in place of r_i); the replay also
+  // composes the chunk's backward map, in forward order G <- G o (y -> d_i - c'_i y)
   Aff<T> M{T(1), T(0)};
   for (int i = i0; i < i1; ++i) {
     const T inv = cl_inv<T>(L, i, n);
     M = aff_after(Aff<T>{-(al * inv), sd[cpad(i, lg)] * inv}, M);
   }
   T d = block_carry<T, true, NWV>(M, sWa, sWb);
+  Aff<T> Mb{T(1), T(0)};
   for (int i = i0; i < i1; ++i) {
     const int o = cpad(i, lg);
     d = (sd[o] - al * d) * cl_inv<T>(L, i, n);
     sd[o] = d;
+    Mb = Aff<T>{-(Mb.a * cl_cp<T>(L, i, n)), Mb.a * d + Mb.b};
   }
-  // backward sweep: compose from the chunk's end, scan from the last thread, replay
-  Aff<T> Mb{T(1), T(0)};
-  for (int i = i1 - 1; i >= i0; --i) Mb = aff_after(Aff<T>{-cl_cp<T>(L, i, n), sd[cpad(i, lg)]}, Mb);
+  // backward sweep: scan from the last thread, replay
   T y = block_carry<T, false, NWV>(Mb, sWa, sWb);
   for (int i = i1 - 1; i >= i0; --i) {
     const int o = cpad(i, lg);
@@ -229,11 +230,17 @@ __global__ __launch_bounds__(64 * NWV) void k_cline(CompactArgs<T> A, CompactLin
 // y-lines and the update.  A workgroup takes CW adjacent columns: lane l of a
 // wave works on column l mod CW and chunk slot l / CW, so a wave's loads are
 // 64 / CW row segments of CW consecutive values, and the NW waves together
-// split each column into NW * 64 / CW chunks.  The chunks exchange their
-// affine maps through LDS, then replay.  The right-hand side comes from a
-// sliding window of 2N+1 values per column; d and y go through a scratch
-// plane.  The last pass forms chi~ = chi - a [(chi - F_x) + (chi - F_y)] with
-// both directions' Sherman-Morrison corrections.  grid = (column blocks, 3).
+// split each column into NW * 64 / CW chunks.  Three passes per chunk:
+//   1. compose the forward map of the chunk (right-hand side from a sliding
+//      window of 2N+1 values per column);
+//   2. with the carry from the chunks above (through LDS), replay: d to a
+//      scratch plane, and compose the chunk's backward map on the way (in
+//      forward order, G <- G o (y -> d_i - c'_i y));
+//   3. with the carry from the chunks below, replay backward and write
+//      chi~ = chi - a [(chi - F_x) + (chi - F_y)] directly, both directions'
+//      Sherman-Morrison corrections applied: y_0 and y_{n-1}, which the
+//      correction needs, are known once the backward carries are.
+// grid = (column blocks, 3).
 template <typename T, int N, int NW, int CW>
 __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T> A,
                                                      const T* __restrict__ c0,
@@ -280,10 +287,10 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
     for (int k = 1; k <= N; ++k) r = r + ah[k] * (win[N + k] + win[N - k]);
     return r;
   };
-  // The serial passes take the next CB window values / scratch values in one
-  // batch of independent loads, so that their latency is paid once per batch.
+  // The serial passes take the next CB values of each operand in one batch of
+  // independent loads, so that their latency is paid once per batch.
   constexpr int CB = 8;
-  // forward sweep
+  // 1. forward map of the chunk
   Aff<T> M{T(1), T(0)};
   if (i0 < i1) load_win(i0);
   for (int base = i0; base < i1; base += CB) {
@@ -307,6 +314,8 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
   T d = T(0);
   for (int k = 0; k < q; ++k) d = sA[k][col] * d + sB[k][col];
   __syncthreads();
+  // 2. forward replay, backward map of the chunk
+  Aff<T> G{T(1), T(0)};
   if (i0 < i1) load_win(i0);
   for (int base = i0; base < i1; base += CB) {
     T nv[CB];
@@ -317,56 +326,49 @@ __global__ __launch_bounds__(64 * NW) void k_cline_y(KParams<T> P, CompactArgs<T
       if (base + j < i1) {
         d = (rhs() - al * d) * cl_inv<T>(L, base + j, n);
         if (live) sc[(long long)(base + j) * nx + xs] = d;
+        G = Aff<T>{-(G.a * cl_cp<T>(L, base + j, n)), G.a * d + G.b};
 #pragma unroll
         for (int k = 0; k < 2 * N; ++k) win[k] = win[k + 1];
         win[2 * N] = nv[j];
       }
     }
   }
-  // backward sweep
-  Aff<T> Mb{T(1), T(0)};
-  for (int top = i1 - 1; top >= i0; top -= CB) {
-    T v[CB];
-#pragma unroll
-    for (int j = 0; j < CB; ++j)
-      if (top - j >= i0) v[j] = sc[(long long)(top - j) * nx + xs];
-#pragma unroll
-    for (int j = 0; j < CB; ++j)
-      if (top - j >= i0) Mb = aff_after(Aff<T>{-cl_cp<T>(L, top - j, n), v[j]}, Mb);
-  }
-  sA[q][col] = Mb.a;
-  sB[q][col] = Mb.b;
+  sA[q][col] = G.a;
+  sB[q][col] = G.b;
   __syncthreads();
   T y = T(0);
   for (int k = NCH - 1; k > q; --k) y = sA[k][col] * y + sB[k][col];
+  // y_{n-1} and y_0 of the column, from the chunks that hold them
+  if (i0 < i1 && i1 == n) sYl[col] = d - cl_cp<T>(L, n - 1, n) * y;
+  if (i0 == 0 && i1 > 0) sY0[col] = G.a * y + G.b;
+  __syncthreads();
+  T fct = T(0);
+  if (L.cyclic) fct = (sY0[col] + T(L.fac) * sYl[col]) / T(L.den);
+  if (!live) return;
+  // 3. backward replay and the update
+  const T a = P.fa;
+  const double* fcx = fctx + (long long)f * n;
   for (int top = i1 - 1; top >= i0; top -= CB) {
-    T v[CB];
+    T v[CB], ch[CB], fv[CB];
 #pragma unroll
     for (int j = 0; j < CB; ++j)
-      if (top - j >= i0) v[j] = sc[(long long)(top - j) * nx + xs];
+      if (top - j >= i0) {
+        const long long o = (long long)(top - j) * nx + x;
+        v[j] = sc[o];
+        ch[j] = src[o];
+        fv[j] = fxf[o];
+      }
 #pragma unroll
     for (int j = 0; j < CB; ++j)
       if (top - j >= i0) {
         const int i = top - j;
         y = v[j] - cl_cp<T>(L, i, n) * y;
-        if (live) sc[(long long)i * nx + xs] = y;
-        if (i == n - 1) sYl[col] = y;
-        if (i == 0) sY0[col] = y;
+        T fy = y;
+        if (L.cyclic) fy = fy - fct * T(L.z[i]);
+        T fxv = fv[j];
+        if (Lx.cyclic) fxv = fxv - T(fcx[i]) * T(Lx.z[x]);
+        dst[(long long)i * nx + x] = ch[j] - a * ((ch[j] - fxv) + (ch[j] - fy));
       }
-  }
-  __syncthreads();
-  T fct = T(0);
-  if (L.cyclic) fct = (sY0[col] + T(L.fac) * sYl[col]) / T(L.den);
-  if (!live) return;
-  const T a = P.fa;
-  for (int i = i0; i < i1; ++i) {
-    const long long o = (long long)i * nx + x;
-    T fy = sc[o];
-    if (L.cyclic) fy = fy - fct * T(L.z[i]);
-    T fxv = fxf[o];
-    if (Lx.cyclic) fxv = fxv - T(fctx[(long long)f * n + i]) * T(Lx.z[x]);
-    const T ch = src[o];
-    dst[o] = ch - a * ((ch - fxv) + (ch - fy));
   }
 }
 

@@ -282,28 +282,47 @@ CompactArgs<T> compact_args(const lbm2p_ctx* c) {
   return A;
 }
 
+// Chunk length (log2) per thread of an x-line of nx nodes on NWV waves: the
+// power of two >= nx / (64 NWV); and the line's padded LDS size.
+template <int NWV>
+inline int cline_lg(int nx) {
+  int lg = 0;
+  while ((64 * NWV << lg) < nx) ++lg;
+  return lg;
+}
+template <typename T, int NWV>
+inline size_t cline_lds(int nx) {
+  const int lg = cline_lg<NWV>(nx);
+  return ((size_t)nx + ((size_t)nx >> lg) + 1) * sizeof(T);
+}
+
+template <typename T, int N, int NWV>
+void launch_cline_x(lbm2p_ctx* c, const CompactArgs<T>& A, const T* p, const T* ux, const T* uy,
+                    T* fx) {
+  const int nx = c->p.nx, ny = c->p.ny;
+  const long long ps = c->ps;
+  k_cline<T, N, NWV><<<3 * ny, 64 * NWV, cline_lds<T, NWV>(nx), c->stream>>>(
+      A, A.line[0][0], A.line[0][1], p, ux, uy, fx, fx + ps, fx + 2 * ps, c->cfct, nx, ny,
+      c->p.wall_x, cline_lg<NWV>(nx));
+}
+
 template <typename T, int N>
 void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, const T* uy,
                     T* po, T* uxo, T* uyo) {
   const CompactArgs<T> A = compact_args<T>(c);
-  const int nx = c->p.nx, ny = c->p.ny;
-  const long long ps = c->ps;
-  T* scr = (T*)c->cscratch;  // d, then y, of the y-lines (three fields)
-  T* fx = scr + 3 * ps;      // F_x of the three fields
-  double* fctx = c->cfct;
-  hipStream_t st = c->stream;
-  // chunk length per thread of the x-line solve: the power of two >= nx / 256
-  constexpr int NWV = 4;
-  int lg = 0;
-  while ((64 * NWV << lg) < nx) ++lg;
-  const size_t shx = ((size_t)nx + ((size_t)nx >> lg) + 1) * sizeof(T);
-  k_cline<T, N, NWV><<<3 * ny, 64 * NWV, shx, st>>>(A, A.line[0][0], A.line[0][1], p, ux, uy, fx,
-                                                    fx + ps, fx + 2 * ps, fctx, nx, ny,
-                                                    c->p.wall_x, lg);
+  const int nx = c->p.nx;
+  T* scr = (T*)c->cscratch;  // d of the y-lines (three fields)
+  T* fx = scr + 3 * c->ps;   // F_x of the three fields
+  // x-lines: 4 waves per line; FP64 lines take 8 when the padded line fits in
+  // 64 KB of LDS (measured faster at 4096 in FP64, slower in FP32)
+  if (sizeof(T) == 8 && cline_lds<T, 8>(nx) <= 65536)
+    launch_cline_x<T, N, 8>(c, A, p, ux, uy, fx);
+  else
+    launch_cline_x<T, N, 4>(c, A, p, ux, uy, fx);
   // y-lines: 16 waves per workgroup, CW columns per workgroup
   constexpr int NW = 16, CW = LBM2P_CLINE_Y_CW;
-  k_cline_y<T, N, NW, CW><<<dim3((nx + CW - 1) / CW, 3), 64 * NW, 0, st>>>(
-      K, A, p, ux, uy, fx, scr, fctx, po, uxo, uyo);
+  k_cline_y<T, N, NW, CW><<<dim3((nx + CW - 1) / CW, 3), 64 * NW, 0, c->stream>>>(
+      K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
 }
 
 template <typename T>
@@ -322,27 +341,25 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
     const int par = c->parity;
     {
       ProfScope ps(c, PASS_GATHER);
+      // while recording for the adjoint, the gather also keeps m_7, m_8 of the
+      // pre-collision g (the g-relaxation rate's derivative needs them)
+      T* m7 = c->rec && p.coupled ? (T*)c->rec_m7 : nullptr;
+      T* m8 = c->rec && p.coupled ? (T*)c->rec_m8 : nullptr;
       if (p.coupled) {
         if (par == 0)
           k_gather<T, 0, true><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, (T*)c->praw,
-                                                             (T*)c->jx, (T*)c->jy);
+                                                             (T*)c->jx, (T*)c->jy, m7, m8);
         else
           k_gather<T, 1, true><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, (T*)c->praw,
-                                                             (T*)c->jx, (T*)c->jy);
+                                                             (T*)c->jx, (T*)c->jy, m7, m8);
       } else {
         if (par == 0)
           k_gather<T, 0, false><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, nullptr, nullptr,
-                                                              nullptr);
+                                                              nullptr, nullptr, nullptr);
         else
           k_gather<T, 1, false><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, nullptr, nullptr,
-                                                              nullptr);
+                                                              nullptr, nullptr, nullptr);
       }
-    }
-    if (c->rec && p.coupled) {
-      if (par == 0)
-        k_rec_m78<T, 0><<<blocks1d(n), 256, 0, st>>>(K, Ag, (T*)c->rec_m7, (T*)c->rec_m8);
-      else
-        k_rec_m78<T, 1><<<blocks1d(n), 256, 0, st>>>(K, Ag, (T*)c->rec_m7, (T*)c->rec_m8);
     }
     if (p.original_ch) {
       k_copy<T><<<blocks1d(n), 256, 0, st>>>(phibar, phi, n);

@@ -167,12 +167,15 @@ __device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[
 }
 
 // ------------------------------------------------------------ a1: gather
-// phi_bar = sum f_i (eq:compute_phi), p = c_s^2 sum g_i (Eq:p), j = sum g_i c_i
+// phi_bar = sum f_i (eq:compute_phi), p = c_s^2 sum g_i (Eq:p), j = sum g_i c_i;
+// with m7, m8 given, also the moments m_7 = g1 - g2 + g3 - g4 and
+// m_8 = g5 - g6 + g7 - g8 of eq:D2Q9MRT
 template <typename T, int PAR, bool COUPLED>
 __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
                                                 const T* __restrict__ Ag, T* __restrict__ phibar,
                                                 T* __restrict__ praw, T* __restrict__ jx,
-                                                T* __restrict__ jy) {
+                                                T* __restrict__ jy, T* __restrict__ m7,
+                                                T* __restrict__ m8) {
   const long long n = (long long)P.nx * P.ny;
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
@@ -205,6 +208,10 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   ay = ay - g[8];
   jx[id] = ax;
   jy[id] = ay;
+  if (m7) {
+    m7[id] = ((g[1] - g[2]) + g[3]) - g[4];
+    m8[id] = ((g[5] - g[6]) + g[7]) - g[8];
+  }
 }
 
 // ------------------------------------------------- a2: FD sub-step stage

@@ -131,6 +131,22 @@ def test_compact_filter_variant(kw):
         _compare_state(sim, st, label=f"{kw} step {n}")
 
 
+@pytest.mark.parametrize("nx,ny,kw", [
+    (300, 520, dict(compact=True, compact_n=5, compact_alpha=0.45)),
+    (520, 300, dict(compact=True, compact_n=4, compact_alpha=0.4, wall_x=True, wall_y=True)),
+])
+def test_compact_filter_multichunk(nx, ny, kw):
+    """Compact filter on lattices whose lines span many chunks of the parallel
+    line solves (several rows per chunk, a ragged last chunk, partial column
+    blocks), against the oracle's solves."""
+    wl = droplet_case(nx, ny, seed=11, **kw)
+    st, prm = oracle_init(wl)
+    sim = gpu_sim(wl)
+    st = oracle.run(st, prm, 2)
+    sim.step(2)
+    _compare_state(sim, st, label=f"{nx}x{ny} {kw}")
+
+
 def test_minimum_size_and_zero_steps():
     wl = droplet_case(16, 16, seed=4, R=5.0, wall_y=True)
     st, prm = oracle_init(wl)

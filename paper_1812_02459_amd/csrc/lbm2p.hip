@@ -57,7 +57,7 @@ size_t n_planes(const lbm2p_params* p) {
   return p->coupled ? 9 + 4 + 4 + 9 + 4 + 4 : 9 + 4 + 4;
 }
 
-size_t compact_planes(const lbm2p_params* p) { return (p->coupled && p->compact) ? 9 : 0; }
+size_t compact_planes(const lbm2p_params* p) { return (p->coupled && p->compact) ? 6 : 0; }
 
 size_t compact_table_doubles(const lbm2p_params* p) {
   if (!(p->coupled && p->compact)) return 0;

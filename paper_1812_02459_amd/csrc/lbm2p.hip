@@ -309,7 +309,7 @@ int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t
                                   size_t* bytes) {
   const int e = validate(p);
   if (e) return e;
-  if (!bytes || nsteps < 0 || ckpt_every < 1 || p->compact) return LBM2P_EINVAL;
+  if (!bytes || nsteps < 0 || ckpt_every < 1) return LBM2P_EINVAL;
   const AdjLayout L = adj_layout(*p, plane_stride(p), (long long)p->nx * p->ny,
                                  p->precision ? 4 : 8, nsteps, ckpt_every);
   *bytes = L.total;
@@ -318,7 +318,6 @@ int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t
 
 int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes) {
   if (!c || nsteps < 0 || ckpt_every < 1 || !d_ws || ((uintptr_t)d_ws & 255)) return LBM2P_EINVAL;
-  if (c->p.compact) return LBM2P_EINVAL;
   if (!c->inited) return LBM2P_ESTATE;
   const AdjLayout L = adj_layout(c->p, c->ps, c->n, c->esz, nsteps, ckpt_every);
   if (bytes < L.total) return LBM2P_ENOSPACE;

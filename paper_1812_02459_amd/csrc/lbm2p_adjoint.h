@@ -532,11 +532,14 @@ __global__ __launch_bounds__(NT) void k_adj_collide(
 // N: local parts, the next state's u~ adjoint (u~ is also the next state's
 // velocity), and the transposed gradients of the collision's grad u and
 // grad p adjoints; then chi_bar = chi~_bar - a F^T chi~_bar (the explicit
-// filter's stencil is symmetric; N = 0: no filter).
+// filter's stencil is symmetric; N = 0: no filter, the outputs are the
+// adjoints of p~, u~ themselves).  Outputs to (op, oux, ouy); with N = 0 a
+// tile reads only its own nodes of lp_*, so the outputs may be lp_*.
 template <typename T, int N, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
                                                      const T* __restrict__ Uoix,
-                                                     const T* __restrict__ Uoiy, AdjWork<T> Wk) {
+                                                     const T* __restrict__ Uoiy, AdjWork<T> Wk,
+                                                     T* op, T* oux, T* ouy) {
   constexpr int WN = TX + 2 * N, HN = TY + 2 * N, WB = WN + 2, HB = HN + 2;
   __shared__ T sB[2][WB * HB];
   __shared__ T sPt[WN * HN], sUx[WN * HN], sUy[WN * HN];
@@ -588,9 +591,9 @@ __global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
         for (int j = -N + 1; j <= N; ++j) sy = sy + dd[j < 0 ? -j : j] * t(lx, ly + j);
         r = r - a * (sx + sy);
       }
-      if (f == 0) Wk.praw_b[id] = r;
-      else if (f == 1) Wk.ukx_b[id] = r;
-      else Wk.uky_b[id] = r;
+      if (f == 0) op[id] = r;
+      else if (f == 1) oux[id] = r;
+      else ouy[id] = r;
     }
   }
 }

@@ -217,12 +217,30 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
       launch_adj_collide<T, true, false>(c, K, C, Wk, sl, sl.utx, sl.uty, uox, uoy, Afi, Agi, pd,
                                          Afo, Ago, Uox, Uoy);
     const Tiles<FIL_TX, FIL_TY> tf(p);
-    switch (p.filter_n ? c->fn : 0) {
-      case 0: k_adj_filter_t<T, 0, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      case 2: k_adj_filter_t<T, 2, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      case 3: k_adj_filter_t<T, 3, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      case 4: k_adj_filter_t<T, 4, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
-      default: k_adj_filter_t<T, 5, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk); break;
+    T* ob[3] = {Wk.praw_b, Wk.ukx_b, Wk.uky_b};
+    if (p.compact) {
+      // The compact filter per direction, F = A^-1 B, is self-adjoint: the line
+      // matrix A and the right-hand-side stencil B are both symmetric stencils
+      // on the mirrored (wall) or periodic line, so they commute and
+      // (A^-1 B)^T = B A^-1 = A^-1 B.  The reverse of the update is therefore
+      // the update itself, applied to the adjoints of p~, u~ (same parities).
+      k_adj_filter_t<T, 0, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(
+          K, tf.tx, Uix, Uiy, Wk, Wk.lp_p, Wk.lp_ux, Wk.lp_uy);
+      switch (p.compact_n) {
+        case 1: launch_compact<T, 1>(c, K, Wk.lp_p, Wk.lp_ux, Wk.lp_uy, ob[0], ob[1], ob[2]); break;
+        case 2: launch_compact<T, 2>(c, K, Wk.lp_p, Wk.lp_ux, Wk.lp_uy, ob[0], ob[1], ob[2]); break;
+        case 3: launch_compact<T, 3>(c, K, Wk.lp_p, Wk.lp_ux, Wk.lp_uy, ob[0], ob[1], ob[2]); break;
+        case 4: launch_compact<T, 4>(c, K, Wk.lp_p, Wk.lp_ux, Wk.lp_uy, ob[0], ob[1], ob[2]); break;
+        default: launch_compact<T, 5>(c, K, Wk.lp_p, Wk.lp_ux, Wk.lp_uy, ob[0], ob[1], ob[2]); break;
+      }
+    } else {
+      switch (p.filter_n ? c->fn : 0) {
+        case 0: k_adj_filter_t<T, 0, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 2: k_adj_filter_t<T, 2, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 3: k_adj_filter_t<T, 3, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 4: k_adj_filter_t<T, 4, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        default: k_adj_filter_t<T, 5, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+      }
     }
     // velocity sweeps last to first; sweep k reads u^k (u^0 = u~^n)
     int cur = 0;

@@ -87,8 +87,9 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
     for bad in [dict(nsteps=-1, k=4), dict(nsteps=10, k=0)]:
         with pytest.raises(B.LBMError, match="invalid argument"):
             B.lbm2p_adjoint_workspace_bytes(p, bad["nsteps"], bad["k"])
-    with pytest.raises(B.LBMError, match="invalid argument"):  # no adjoint of the compact filter
-        B.lbm2p_adjoint_workspace_bytes(B.make_params(dict(ok, compact=True), 0), 10, 4)
+    # the compact filter has an adjoint too; its workspace matches the explicit filter's
+    nca = B.lbm2p_adjoint_workspace_bytes(B.make_params(dict(ok, compact=True), 0), 10, 4)
+    assert nca == B.lbm2p_adjoint_workspace_bytes(B.make_params(ok, 0), 10, 4)
     need = B.lbm2p_workspace_bytes(p)
     buf = ctypes.create_string_buffer(need + 512)
     aligned = (ctypes.addressof(buf) + 255) // 256 * 256

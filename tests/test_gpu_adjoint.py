@@ -85,6 +85,9 @@ ONE_STEP_CASES = [
     dict(filter_n=0, K=1),
     dict(original_ch=True, filter_n=5),
     dict(wall_x=True, filter_n=9, filter_a=0.3, K=4),
+    dict(compact=True, compact_n=5, compact_alpha=0.45),
+    dict(compact=True, compact_n=3, compact_alpha=0.4, wall_x=True, wall_y=True, gy=-1e-5),
+    dict(compact=True, compact_n=2, compact_alpha=0.3, wall_y=True, filter_a=0.8, K=3),
 ]
 
 
@@ -134,7 +137,7 @@ def _oracle_run_grad(wl, nsteps, cphi):
     return dict(phi0=g[0], sigma=float(g[1]), M=float(g[2]))
 
 
-@pytest.mark.parametrize("case", ["walls", "periodic", "ch_only"])
+@pytest.mark.parametrize("case", ["walls", "periodic", "ch_only", "compact_walls"])
 def test_checkpointed_run_gradient(case):
     """Several segments (7 steps, a checkpoint every 3), the loss on the last
     phi, gradients down to phi0 through the equilibrium initial state."""
@@ -142,6 +145,9 @@ def test_checkpointed_run_gradient(case):
         wl = droplet_case(32, 24, seed=5, wall_x=True, wall_y=True, gy=-1e-5)
     elif case == "periodic":
         wl = droplet_case(28, 32, seed=6, K=3)
+    elif case == "compact_walls":
+        wl = droplet_case(32, 24, seed=7, wall_y=True, compact=True, compact_n=4,
+                          compact_alpha=0.45)
     else:
         wl = I.vortex(n=32)
     ny, nx = wl.phi0.shape

@@ -176,6 +176,22 @@ def test_compact_wall_symmetry_and_transfer_in_interior():
     assert np.allclose(out, T * w, atol=1e-13)
 
 
+@pytest.mark.parametrize("wall,odd", [(False, False), (True, False), (True, True)])
+@pytest.mark.parametrize("N,alpha", [(5, 0.45), (3, 0.3), (1, -0.2)])
+def test_compact_lowpass_is_self_adjoint(wall, odd, N, alpha):
+    """The per-direction compact low-pass is a symmetric matrix on periodic
+    lines and on lines with half-way mirror ghosts of either parity: the line
+    matrix and the right-hand-side stencil are symmetric stencils on the same
+    extended line, so they commute.  The library's adjoint of the compact
+    filter relies on this (its reverse is the filter itself)."""
+    n = 23
+    Mx = compact.lowpass(torch.eye(n, dtype=torch.float64), 1, N, alpha, wall=wall, odd=odd)
+    M = Mx.numpy()                       # row k = lowpass of the unit vector e_k
+    assert np.abs(M - M.T).max() <= 1e-14 * np.abs(M).max()
+    # and not trivially: the filter is not a multiple of the identity
+    assert np.abs(M - np.diag(np.diag(M))).max() > 1e-3
+
+
 def test_sqrt_is_correctly_rounded():
     """The oracle's sqrt returns the double nearest to the exact square root
     (checked with exact rational arithmetic on random and extreme inputs)."""

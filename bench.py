@@ -166,14 +166,17 @@ def variant_legs(wl, steps, warmup, fp64=True):
     return out
 
 
-def adjoint_cost(precision, nsteps, k=64, warmup=64):
+def adjoint_cost(precision, nsteps, k=64, warmup=64, compact=False):
     """Forward step time against the adjoint's time per step (segment recompute
     plus reverse sweep, checkpoints every k steps) on the closed-box rising
-    bubble, 256 x 1024, R = 32, loss seed 2 (phi_T - phi*)/N."""
+    bubble, 256 x 1024, R = 32, loss seed 2 (phi_T - phi*)/N; with compact,
+    the compact tridiagonal filter (N = 5, alpha = 0.45) in place of SF-11."""
     import torch
     from paper_1812_02459_amd import inputs as I
     from paper_1812_02459_amd.binding import Sim
     wl = I.rising_bubble()
+    if compact:
+        wl.params = dict(wl.params, compact=True, compact_n=5, compact_alpha=0.45)
     sim = Sim(wl.params, precision=precision)
     sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
     sim.step(warmup)
@@ -260,6 +263,7 @@ def main():
         res = {"fp32": adjoint_cost(1, args.adj_steps)}
         if not args.no_fp64:
             res["fp64"] = adjoint_cost(0, args.adj_steps)
+        res["fp32_compact_filter"] = adjoint_cost(1, args.adj_steps, compact=True)
         print(json.dumps({"adjoint": res}), flush=True)
         return
     t0 = time.perf_counter()
@@ -285,8 +289,10 @@ def main():
                "fp32": adjoint_cost(1, args.adj_steps)}
         if not args.no_fp64:
             adj["fp64"] = adjoint_cost(0, args.adj_steps)
+        adj["fp32_compact_filter"] = adjoint_cost(1, args.adj_steps, compact=True)
         print(f"# adjoint/forward: fp32 {adj['fp32']['ratio']:.2f}"
-              + (f", fp64 {adj['fp64']['ratio']:.2f}" if "fp64" in adj else ""),
+              + (f", fp64 {adj['fp64']['ratio']:.2f}" if "fp64" in adj else "")
+              + f", fp32 compact filter {adj['fp32_compact_filter']['ratio']:.2f}",
               file=sys.stderr, flush=True)
     variants = None
     if not args.no_variants:

@@ -217,8 +217,10 @@ def _c5_loss_run(Sim, wl, prm, nsteps, precision, target, phi0=None, record=Fals
     return sim, phiT, L
 
 
-@pytest.mark.parametrize("nsteps,bar", [(2000, 1e-6), (4000, 5e-5)])
-def test_c5_gradient_vs_central_differences_fp64(nsteps, bar):
+@pytest.mark.parametrize("nsteps,bar,compact,h_phi", [(2000, 1e-6, False, 1e-5),
+                                                      (4000, 5e-5, False, 1e-5),
+                                                      (2000, 1e-6, True, 1e-6)])
+def test_c5_gradient_vs_central_differences_fp64(nsteps, bar, compact, h_phi):
     """Closed-box rising bubble 256 x 1024, R = 32, checkpoints every 64:
     dL/dsigma, dL/dM and dL/dphi0 . v of L = mean((phi_T - phi*_T)^2), phi*_T
     from sigma* = sigma_0 U(0.5, 2) (seed 0), against central differences of
@@ -232,9 +234,16 @@ def test_c5_gradient_vs_central_differences_fp64(nsteps, bar):
     one-sided slopes.  Later, the gas interior drifts below -1 and crosses the
     kink during the run: the agreement is 1e-6 or better up to 2000 steps and
     limited near 1e-5 at 4000 (measured with h from 1e-3 to 1e-6: the error
-    falls with h down to that floor, as for kinks, not rounding)."""
+    falls with h down to that floor, as for kinks, not rounding).  The compact
+    case runs the compact tridiagonal filter (N = 5, alpha = 0.45) in place of
+    SF-11, with h = 1e-6 along v: measured over h = 1e-4, 1e-5, 1e-6 at 2000
+    steps, the phi0 difference is off by 4e-4, 1.3e-5, 2e-8 (SF-11: 1e-4,
+    5e-8, 1.5e-7) while phi_T reaches -1.002 below the kink -- the larger
+    steps straddle it.  Rounding of the difference at h = 1e-6 is ~1e-10."""
     from paper_1812_02459_amd.binding import Sim
     wl = I.rising_bubble()
+    if compact:
+        wl.params = dict(wl.params, compact=True, compact_n=5, compact_alpha=0.45)
     rng = np.random.default_rng(0)
     sig0, M0 = wl.params["sigma"], wl.params["M"]
     sig_star = sig0 * rng.uniform(0.5, 2.0)
@@ -249,7 +258,7 @@ def test_c5_gradient_vs_central_differences_fp64(nsteps, bar):
     v = v / v.norm()
     adj = {"sigma": g["sigma"], "M": g["M"], "phi0.v": float((g["phi0"].cpu() * v).sum())}
     res = {}
-    for name, h in (("sigma", 1e-5 * sig0), ("M", 1e-4 * M0), ("phi0.v", 1e-5)):
+    for name, h in (("sigma", 1e-5 * sig0), ("M", 1e-4 * M0), ("phi0.v", h_phi)):
         Ls = []
         for sgn in (1, -1):
             prm = dict(wl.params)
@@ -265,7 +274,7 @@ def test_c5_gradient_vs_central_differences_fp64(nsteps, bar):
             Ls.append(L)
         fd = (Ls[0] - Ls[1]) / (2 * h)
         res[name] = (adj[name], fd, abs(adj[name] - fd) / abs(fd))
-    print(f"C5 FD check {nsteps} steps: L0 %.6e" % L0,
+    print(f"C5 FD check {nsteps} steps{' compact' if compact else ''}: L0 %.6e" % L0,
           {k: "adj %.9e fd %.9e rel %.2e" % v_ for k, v_ in res.items()}, flush=True)
     for k_, (_, _, rel) in res.items():
         assert rel <= bar, (k_, rel)

@@ -24,11 +24,15 @@ template <typename T>
 struct AdjCfg {
   using Col = AdjTile<16, 1024>;
   using Vel = AdjTile<16, 1024>;
+  using Phi = AdjTile<16, 1024>;
+  using Fil = AdjTile<16, 1024>;
 };
 template <>
 struct AdjCfg<double> {
   using Col = AdjTile<8, 512>;
   using Vel = AdjTile<8, 512>;
+  using Phi = AdjTile<16, 1024>;   // 512 or 256 threads measured slower
+  using Fil = AdjTile<16, 1024>;
 };
 
 // planes of one recorded step
@@ -208,7 +212,9 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
   T* Uox = Ao + sp * ps;
   T* Uoy = Uox + ps;
   const bool pend = pd.phi != nullptr;
-  const Tiles<FD_TX, FD_TY> t16(p);
+  using AdjPhi = typename AdjCfg<T>::Phi;
+  using AdjFil = typename AdjCfg<T>::Fil;
+  const Tiles<64, AdjPhi::TY> t16(p);
   if (p.coupled) {
     if (pend)
       launch_adj_collide<T, true, true>(c, K, C, Wk, sl, sl.utx, sl.uty, uox, uoy, Afi, Agi, pd,
@@ -216,7 +222,7 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
     else
       launch_adj_collide<T, true, false>(c, K, C, Wk, sl, sl.utx, sl.uty, uox, uoy, Afi, Agi, pd,
                                          Afo, Ago, Uox, Uoy);
-    const Tiles<FIL_TX, FIL_TY> tf(p);
+    const Tiles<64, AdjFil::TY> tf(p);
     T* ob[3] = {Wk.praw_b, Wk.ukx_b, Wk.uky_b};
     if (p.compact) {
       // The compact filter per direction, F = A^-1 B, is self-adjoint: the line
@@ -224,7 +230,7 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
       // on the mirrored (wall) or periodic line, so they commute and
       // (A^-1 B)^T = B A^-1 = A^-1 B.  The reverse of the update is therefore
       // the update itself, applied to the adjoints of p~, u~ (same parities).
-      k_adj_filter_t<T, 0, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(
+      k_adj_filter_t<T, 0, 64, AdjFil::TY, AdjFil::NT><<<tf.grid(), AdjFil::NT, 0, st>>>(
           K, tf.tx, Uix, Uiy, Wk, Wk.lp_p, Wk.lp_ux, Wk.lp_uy);
       switch (p.compact_n) {
         case 1: launch_compact<T, 1>(c, K, Wk.lp_p, Wk.lp_ux, Wk.lp_uy, ob[0], ob[1], ob[2]); break;
@@ -235,11 +241,11 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
       }
     } else {
       switch (p.filter_n ? c->fn : 0) {
-        case 0: k_adj_filter_t<T, 0, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
-        case 2: k_adj_filter_t<T, 2, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
-        case 3: k_adj_filter_t<T, 3, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
-        case 4: k_adj_filter_t<T, 4, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
-        default: k_adj_filter_t<T, 5, FIL_TX, FIL_TY, 1024><<<tf.grid(), 1024, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 0: k_adj_filter_t<T, 0, 64, AdjFil::TY, AdjFil::NT><<<tf.grid(), AdjFil::NT, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 2: k_adj_filter_t<T, 2, 64, AdjFil::TY, AdjFil::NT><<<tf.grid(), AdjFil::NT, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 3: k_adj_filter_t<T, 3, 64, AdjFil::TY, AdjFil::NT><<<tf.grid(), AdjFil::NT, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        case 4: k_adj_filter_t<T, 4, 64, AdjFil::TY, AdjFil::NT><<<tf.grid(), AdjFil::NT, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
+        default: k_adj_filter_t<T, 5, 64, AdjFil::TY, AdjFil::NT><<<tf.grid(), AdjFil::NT, 0, st>>>(K, tf.tx, Uix, Uiy, Wk, ob[0], ob[1], ob[2]); break;
       }
     }
     // velocity sweeps last to first; sweep k reads u^k (u^0 = u~^n)
@@ -259,7 +265,7 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
         cur = 1 - cur;
       }
     }
-    k_adj_phi<T, true, FD_TX, FD_TY, 1024><<<t16.grid(), 1024, 0, st>>>(K, C, t16.tx, sl.phi, cur, seed,
+    k_adj_phi<T, true, 64, AdjPhi::TY, AdjPhi::NT><<<t16.grid(), AdjPhi::NT, 0, st>>>(K, C, t16.tx, sl.phi, cur, seed,
                                                                  Uox, Uoy, Wk);
   } else {
     const T* ux = (const T*)c->U[0][0];
@@ -270,7 +276,7 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
     else
       launch_adj_collide<T, false, false>(c, K, C, Wk, sl, ux, uy, ux, uy, Afi, nullptr, pd, Afo,
                                           nullptr, nullptr, nullptr);
-    k_adj_phi<T, false, FD_TX, FD_TY, 1024><<<t16.grid(), 1024, 0, st>>>(K, C, t16.tx, sl.phi, 0, seed,
+    k_adj_phi<T, false, 64, AdjPhi::TY, AdjPhi::NT><<<t16.grid(), AdjPhi::NT, 0, st>>>(K, C, t16.tx, sl.phi, 0, seed,
                                                                   nullptr, nullptr, Wk);
   }
   const T* phib = Wk.phi_b;

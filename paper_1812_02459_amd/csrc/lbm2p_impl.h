@@ -391,21 +391,19 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       int done = 0, launch = 0;
       while (done < p.K) {
         // two sweeps per launch, one for an odd remainder; when recording for
-        // the adjoint, one sweep per launch, each iterate to its own plane
-        T* ox = (T*)(c->rec ? c->rec_uk[launch][0] : c->uk[launch & 1][0]);
-        T* oy = (T*)(c->rec ? c->rec_uk[launch][1] : c->uk[launch & 1][1]);
+        // the adjoint, every iterate u^{s+1} goes to its own plane rec_uk[s]
+        // (the two-sweep kernel then also writes its first sweep's result)
+        const bool two = p.K - done >= 2;
+        const int last = done + (two ? 1 : 0);
+        T* ox = (T*)(c->rec ? c->rec_uk[last][0] : c->uk[launch & 1][0]);
+        T* oy = (T*)(c->rec ? c->rec_uk[last][1] : c->uk[launch & 1][1]);
+        T* o1x = (T*)(c->rec && two ? c->rec_uk[done][0] : nullptr);
+        T* o1y = (T*)(c->rec && two ? c->rec_uk[done][1] : nullptr);
         ProfScope ps(c, PASS_VEL);
-        // (FP64: one sweep per launch -- the two-sweep kernel's LDS footprint
-        // costs more occupancy than its saved traffic is worth in double)
-        bool two = false;
-        if constexpr (sizeof(T) == 4) {
-          if (p.K - done >= 2 && !c->rec) {
-            k_vel2<T, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
-                K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
-            two = true;
-          }
-        }
-        if (!two)
+        if (two)
+          k_vel2<T, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
+              K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
+        else
           k_vel<T, 1, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
               K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
         done += two ? 2 : 1;

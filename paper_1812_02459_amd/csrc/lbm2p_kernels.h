@@ -441,20 +441,22 @@ __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* 
   }
 }
 
-// Two velocity sweeps in one launch, for the FP32 step.  phi and p are fixed
+// Two velocity sweeps in one launch.  phi and p are fixed
 // during the sweeps, so F_p + F_s, J = c_J grad mu, grad rho, nu and rho are the
 // same in both: on the tile's own nodes they are evaluated once and kept in
 // registers (each thread owns TX*TY/NT nodes in both sweeps), and the second
 // sweep re-evaluates only the u-dependent F_nu and F_m (F summed in the order
 // (((F_p + F_s) + F_nu) + F_m) + F_g as in node_force).  The first sweep also
 // covers the ring of nodes around the tile, which the second sweep's stencils
-// read.
+// read.  With u1x, u1y given, the first sweep's iterate is written there too
+// (the adjoint keeps every iterate).
 template <typename T, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                               const T* __restrict__ praw, const T* __restrict__ jx,
                                               const T* __restrict__ jy, const T* __restrict__ uxi,
                                               const T* __restrict__ uyi, T* __restrict__ uxo,
-                                              T* __restrict__ uyo) {
+                                              T* __restrict__ uyo, T* __restrict__ u1x,
+                                              T* __restrict__ u1y) {
   static_assert((TX * TY) % NT == 0, "whole tile rows per thread group");
   constexpr int WP = TX + 6, HPH = TY + 6;   // phi, halo 3
   constexpr int WD = TX + 4, HD = TY + 4;    // derived fields and u^0, halo 2
@@ -545,6 +547,11 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     sweep(c[r], tU0x, tU0y, lx, ly, vx, vy);
     sU1x[(ly + 1) * W1 + lx + 1] = vx;
     sU1y[(ly + 1) * W1 + lx + 1] = vy;
+    if (u1x != nullptr && x0 + lx < P.nx && y0 + ly < P.ny) {
+      const int id = (y0 + ly) * P.nx + x0 + lx;
+      u1x[id] = vx;
+      u1y[id] = vy;
+    }
   }
   // the ring: rows -1 and TY (W1 nodes each), then columns -1 and TX
   for (int k = threadIdx.x; k < NRING; k += NT) {

@@ -254,7 +254,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the "
-              "multi-GPU slab decomposition is a design, not part of this build.",
+              "multi-GPU slab decomposition is designed but not implemented.",
               file=sys.stderr)
         sys.exit(2)
     import torch

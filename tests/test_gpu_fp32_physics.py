@@ -31,13 +31,16 @@ from paper_1812_02459_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-OUT = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+# measured values are printed, and also written as JSON to the directory
+# LBM2P_RESULTS_DIR names, when it is set
+OUT = os.environ.get("LBM2P_RESULTS_DIR")
 
 
 def _record(name, data):
-    os.makedirs(OUT, exist_ok=True)
-    with open(os.path.join(OUT, f"fp32_{name}.json"), "w") as fh:
-        json.dump(data, fh, indent=1)
+    if OUT:
+        os.makedirs(OUT, exist_ok=True)
+        with open(os.path.join(OUT, f"fp32_{name}.json"), "w") as fh:
+            json.dump(data, fh, indent=1)
     print(name, json.dumps(data), flush=True)
 
 

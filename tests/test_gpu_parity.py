@@ -1,7 +1,7 @@
 """FP64 parity of the HIP library (through the C-ABI) with the CPU oracle.
 
 Bar: max-norm error relative to the max norm <= 1e-12 for every compared field
-(spec FP64 tolerance).  Sizes span several tiles of every kernel and end
+(the FP64 tolerance the method's GPU path is held to).  Sizes span several tiles of every kernel and end
 in ragged tiles; boundaries periodic, one wall pair and two wall pairs.
 """
 

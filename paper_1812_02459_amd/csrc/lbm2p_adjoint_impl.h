@@ -26,11 +26,13 @@ struct AdjCfg {
   using Vel = AdjTile<16, 1024>;
   using Phi = AdjTile<16, 1024>;
   using Fil = AdjTile<16, 1024>;
+  using Fd = AdjTile<16, 512>;
 };
 template <>
 struct AdjCfg<double> {
   using Col = AdjTile<8, 512>;
-  using Vel = AdjTile<8, 512>;
+  using Vel = AdjTile<16, 1024>;
+  using Fd = AdjTile<16, 1024>;
   using Phi = AdjTile<16, 1024>;   // 512 or 256 threads measured slower
   using Fil = AdjTile<16, 1024>;
 };
@@ -151,6 +153,52 @@ void load_ckpt(lbm2p_ctx* c, const AdjPtrs<T>& A, int i, int parity, bool fields
   c->uo = 0;
 }
 
+// The context's own planes, which a recomputed (or recorded-and-kept) step
+// is rebound away from, slot by slot.
+struct OwnPlanes {
+  void *phibar, *phi1, *phi2, *phi, *praw, *pt;
+  void* U[2][2];
+};
+inline OwnPlanes own_planes(const lbm2p_ctx* c) {
+  return OwnPlanes{c->phibar, c->phi1, c->phi2, c->phi, c->praw, c->pt,
+                   {{c->U[0][0], c->U[0][1]}, {c->U[1][0], c->U[1][1]}}};
+}
+inline void restore_planes(lbm2p_ctx* c, const OwnPlanes& o) {
+  c->phibar = o.phibar;
+  c->phi1 = o.phi1;
+  c->phi2 = o.phi2;
+  c->phi = o.phi;
+  c->praw = o.praw;
+  c->pt = o.pt;
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) c->U[a][b] = o.U[a][b];
+}
+// The next step writes its intermediates to slot j: phi_bar, phi^(1), phi^(2),
+// phi, p, p~, u~ (as the state's next velocity plane), the iterates and m7, m8.
+template <typename T>
+void bind_slot(lbm2p_ctx* c, const AdjPtrs<T>& A, int j) {
+  const lbm2p_params& p = c->p;
+  const Slot<T> sl = A.slot(j, p);
+  c->phibar = sl.phibar;
+  c->phi1 = sl.phi1;
+  c->phi2 = sl.phi2;
+  c->phi = sl.phi;
+  if (p.coupled) {
+    c->praw = sl.praw;
+    c->pt = sl.pt;
+    c->U[1 - c->uo][0] = sl.utx;
+    c->U[1 - c->uo][1] = sl.uty;
+    for (int i = 1; i < p.K; ++i) {
+      c->rec_uk[i - 1][0] = sl.u[i][0];
+      c->rec_uk[i - 1][1] = sl.u[i][1];
+    }
+    c->rec_uk[p.K - 1][0] = c->uk[0][0];
+    c->rec_uk[p.K - 1][1] = c->uk[0][1];
+    c->rec_m7 = sl.m7;
+    c->rec_m8 = sl.m8;
+  }
+}
+
 template <typename T>
 int record_impl(lbm2p_ctx* c, int nsteps, int k) {
   AdjPtrs<T> A{adj_layout(c->p, c->ps, c->n, c->esz, nsteps, k), c->adj_ws};
@@ -159,13 +207,33 @@ int record_impl(lbm2p_ctx* c, int nsteps, int k) {
   c->adj_k = k;
   c->adj_from_init = c->from_init && c->steps == 0;
   c->adj_parity0 = c->parity;
+  c->adj_last_kept = 0;
   save_ckpt<T>(c, A, 0);
+  // The last segment is the first one reversed: its steps write their
+  // intermediates to the slots now, so the adjoint need not recompute it.
+  const int s_last = nsteps > 0 ? (A.L.nseg - 1) * k : 0;
+  const OwnPlanes own = own_planes(c);
   for (int s = 0; s < nsteps; ++s) {
+    if (s >= s_last) {
+      c->rec = 1;
+      bind_slot<T>(c, A, s - s_last);
+    }
     const int e = step_impl<T>(c, 1);
-    if (e) return e;
+    if (e) {
+      c->rec = 0;
+      restore_planes(c, own);
+      return e;
+    }
     if ((s + 1) % k == 0 && s + 1 < nsteps) save_ckpt<T>(c, A, (s + 1) / k);
   }
   save_ckpt<T>(c, A, A.L.nseg);
+  if (nsteps > 0) {
+    // back to the context's own planes, holding the final state
+    c->rec = 0;
+    restore_planes(c, own);
+    load_ckpt<T>(c, A, A.L.nseg, c->adj_parity0 ^ (nsteps & 1), true);
+    c->adj_last_kept = 1;
+  }
   c->adj_steps_end = c->steps;
   c->adj_ready = 1;
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
@@ -281,14 +349,14 @@ Pending<T> adj_step(lbm2p_ctx* c, const AdjPtrs<T>& A, const AdjWork<T>& Wk, con
   }
   const T* phib = Wk.phi_b;
   if (!p.original_ch) {
-    // FP64 tiles are 64 x 8 to keep the stage's LDS footprint under 80 KB
-    constexpr int TY = sizeof(T) == 8 ? 8 : 16;
+    using AdjFd = typename AdjCfg<T>::Fd;
+    constexpr int TY = AdjFd::TY, NTF = AdjFd::NT;
     const Tiles<64, TY> tf(p);
-    k_adj_fd<T, 3, 64, TY, ADJ_NT><<<tf.grid(), ADJ_NT, 0, st>>>(K, C, tf.tx, sl.phi2, Wk.phi_b,
+    k_adj_fd<T, 3, 64, TY, NTF><<<tf.grid(), NTF, 0, st>>>(K, C, tf.tx, sl.phi2, Wk.phi_b,
                                                       T(2.0 / 3.0), Wk);
-    k_adj_fd<T, 2, 64, TY, ADJ_NT><<<tf.grid(), ADJ_NT, 0, st>>>(K, C, tf.tx, sl.phi1, Wk.phi2_b, T(0.25),
+    k_adj_fd<T, 2, 64, TY, NTF><<<tf.grid(), NTF, 0, st>>>(K, C, tf.tx, sl.phi1, Wk.phi2_b, T(0.25),
                                                       Wk);
-    k_adj_fd<T, 1, 64, TY, ADJ_NT><<<tf.grid(), ADJ_NT, 0, st>>>(K, C, tf.tx, sl.phibar, Wk.phi1_b, T(1),
+    k_adj_fd<T, 1, 64, TY, NTF><<<tf.grid(), NTF, 0, st>>>(K, C, tf.tx, sl.phibar, Wk.phi1_b, T(1),
                                                       Wk);
     phib = Wk.phib_b;
   }
@@ -325,48 +393,27 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
     for (int d = 0; d < 2; ++d)
       k_from_f64<T><<<blocks1d(n), 256, 0, st>>>(io->dL_du + d * n, A0 + (sp + d) * ps, n);
   // the context's own planes, rebound per recomputed step
-  void* own_phibar = c->phibar;
-  void* own_phi1 = c->phi1;
-  void* own_phi2 = c->phi2;
-  void* own_phi = c->phi;
-  void* own_praw = c->praw;
-  void* own_pt = c->pt;
-  void* own_U[2][2] = {{c->U[0][0], c->U[0][1]}, {c->U[1][0], c->U[1][1]}};
+  const OwnPlanes own = own_planes(c);
   int ai = 0;
   Pending<T> pd{nullptr, nullptr, nullptr, nullptr};
   for (int seg = A.L.nseg - 1; seg >= 0; --seg) {
     const int s0 = seg * k;
     const int len = std::min(k, nsteps - s0);
-    c->U[0][0] = own_U[0][0];
-    c->U[0][1] = own_U[0][1];
-    c->U[1][0] = own_U[1][0];
-    c->U[1][1] = own_U[1][1];
-    load_ckpt<T>(c, A, seg, c->adj_parity0 ^ (s0 & 1), false);
-    c->rec = 1;
-    for (int j = 0; j < len; ++j) {
-      const Slot<T> sl = A.slot(j, p);
-      c->phibar = sl.phibar;
-      c->phi1 = sl.phi1;
-      c->phi2 = sl.phi2;
-      c->phi = sl.phi;
-      if (p.coupled) {
-        c->praw = sl.praw;
-        c->pt = sl.pt;
-        c->U[1 - c->uo][0] = sl.utx;
-        c->U[1 - c->uo][1] = sl.uty;
-        for (int i = 1; i < p.K; ++i) {
-          c->rec_uk[i - 1][0] = sl.u[i][0];
-          c->rec_uk[i - 1][1] = sl.u[i][1];
+    if (seg == A.L.nseg - 1 && c->adj_last_kept) {
+      // kept by the record; the recomputes below reuse the slots
+      if (A.L.nseg > 1) c->adj_last_kept = 0;
+    } else {
+      restore_planes(c, own);
+      load_ckpt<T>(c, A, seg, c->adj_parity0 ^ (s0 & 1), false);
+      c->rec = 1;
+      for (int j = 0; j < len; ++j) {
+        bind_slot<T>(c, A, j);
+        const int e = step_impl<T>(c, 1);
+        if (e) {
+          c->rec = 0;
+          restore_planes(c, own);
+          return e;
         }
-        c->rec_uk[p.K - 1][0] = c->uk[0][0];
-        c->rec_uk[p.K - 1][1] = c->uk[0][1];
-        c->rec_m7 = sl.m7;
-        c->rec_m8 = sl.m8;
-      }
-      const int e = step_impl<T>(c, 1);
-      if (e) {
-        c->rec = 0;
-        return e;
       }
     }
     c->rec = 0;
@@ -391,14 +438,7 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
     }
   }
   // back to the context's own planes and the recorded final state
-  c->phibar = own_phibar;
-  c->phi1 = own_phi1;
-  c->phi2 = own_phi2;
-  c->phi = own_phi;
-  c->praw = own_praw;
-  c->pt = own_pt;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) c->U[a][b] = own_U[a][b];
+  restore_planes(c, own);
   load_ckpt<T>(c, A, A.L.nseg, c->adj_parity0 ^ (nsteps & 1), true);
   c->steps = c->adj_steps_end;
   // outputs: the first step's gather adjoint completes the initial state's

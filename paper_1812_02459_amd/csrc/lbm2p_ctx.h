@@ -55,6 +55,7 @@ struct lbm2p_ctx {
   char* adj_ws;
   size_t adj_bytes;
   int adj_nsteps, adj_k, adj_from_init, adj_parity0, adj_ready;
+  int adj_last_kept;            // the slots hold the last recorded segment
   long long adj_steps_end;
 };
 

@@ -147,6 +147,21 @@ def test_compact_filter_multichunk(nx, ny, kw):
     _compare_state(sim, st, label=f"{nx}x{ny} {kw}")
 
 
+@pytest.mark.parametrize("nx,ny,kw", [
+    (7680, 16, dict(compact=True, compact_n=5, compact_alpha=0.45, wall_y=True)),
+    (16, 7680, dict(compact=True, compact_n=3, compact_alpha=0.4, wall_x=True)),
+])
+def test_compact_filter_longest_lines(nx, ny, kw):
+    """Compact filter on lines of the maximum length 7680 (the x-line solve
+    stages the whole line in LDS: 64 KB in FP64), both orientations."""
+    wl = droplet_case(nx, ny, seed=12, R=6.0, **kw)
+    st, prm = oracle_init(wl)
+    sim = gpu_sim(wl)
+    st = oracle.run(st, prm, 2)
+    sim.step(2)
+    _compare_state(sim, st, label=f"{nx}x{ny} {kw}")
+
+
 def test_minimum_size_and_zero_steps():
     wl = droplet_case(16, 16, seed=4, R=5.0, wall_y=True)
     st, prm = oracle_init(wl)

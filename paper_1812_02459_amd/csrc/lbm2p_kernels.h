@@ -700,12 +700,20 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
     int rd[9];
     slots<PAR>(P, x, y, rd);
     {
-      T f[9], feq[9], F[9];
+      T f[9], feq[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) f[i] = Af[rd[i]];
       f_eq<T>(ph, tMu(lx, ly), u_x, u_y, P.eta, feq);
-      src_f<T>(ph, ax, ay, F);
-      mrt_collide<T>(f, feq, F, P.s_f);
+      if constexpr (std::is_same<T, float>::value) {
+        // moments of eq:Fi: M F = (0, 0, 0, phi a_x, -phi a_x, phi a_y, -phi a_y, 0, 0)
+        const T pax = ph * ax, pay = ph * ay;
+        const T mF[9] = {T(0), T(0), T(0), pax, -pax, pay, -pay, T(0), T(0)};
+        mrt_collide_ms<T>(f, feq, mF, P.s_f);
+      } else {
+        T F[9];
+        src_f<T>(ph, ax, ay, F);
+        mrt_collide<T>(f, feq, F, P.s_f);
+      }
 #pragma unroll
       for (int i = 0; i < 9; ++i) Af[rd[opp(i)]] = f[i];
     }
@@ -717,18 +725,28 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
       iso_grad<T>(tPt, lx, ly, dpx, dpy);
       const T Frx = qdiv(Fx, rho), Fry = qdiv(Fy, rho);
       const T bx = Frx - dpx, by = Fry - dpy;
-      T g[9], geq[9], G[9], s[9];
+      T g[9], geq[9], s[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = Ag[rd[i]];
       g_eq<T>(p, u_x, u_y, geq);
-      src_g<T>(Frx, Fry, u_x, u_y, bx, by, G);
       const T tau_g = nu * T(3) + T(0.5);
       const T sv = qdiv(T(1), tau_g);
 #pragma unroll
       for (int k = 0; k < 9; ++k) s[k] = P.s_g[k];
       s[7] = sv;
       s[8] = sv;
-      mrt_collide<T>(g, geq, G, s);
+      if constexpr (std::is_same<T, float>::value) {
+        // moments of eq:Gi: M G = (0, 6 b.u, -6 b.u, F_x/rho, -F_x/rho, F_y/rho,
+        // -F_y/rho, 2 (b_x u_x - b_y u_y), b_x u_y + b_y u_x)
+        const T ub6 = T(6) * (u_x * bx + u_y * by);
+        const T mG[9] = {T(0), ub6, -ub6, Frx, -Frx, Fry, -Fry,
+                         T(2) * (bx * u_x - by * u_y), bx * u_y + by * u_x};
+        mrt_collide_ms<T>(g, geq, mG, s);
+      } else {
+        T G[9];
+        src_g<T>(Frx, Fry, u_x, u_y, bx, by, G);
+        mrt_collide<T>(g, geq, G, s);
+      }
 #pragma unroll
       for (int i = 0; i < 9; ++i) Ag[rd[opp(i)]] = g[i];
     }

@@ -86,6 +86,10 @@ typedef struct lbm2p_params {
   double eps;              /* regularisation of |grad phi| in n, >= 0          */
   int32_t original_ch;     /* 1 = no FD sub-step (the original convective CH)  */
   int32_t reserved;        /* must be 0                                        */
+  double p_ref;            /* reference kinematic pressure of the stored g:
+                              the library keeps g_i - 3 w_i p_ref, deviations
+                              from the lattice weights (the state I/O converts;
+                              0 = plain values).  Finite.                     */
 } lbm2p_params;
 
 typedef struct lbm2p_ctx lbm2p_ctx;

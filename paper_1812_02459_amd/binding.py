@@ -45,6 +45,7 @@ class Params(ctypes.Structure):
         ("s_f", ctypes.c_double * 9), ("s_g", ctypes.c_double * 9),
         ("eps", ctypes.c_double),
         ("original_ch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("p_ref", ctypes.c_double),
     ]
 
 
@@ -123,6 +124,7 @@ def make_params(d, precision=0):
         p.s_g[k] = 0.0 if sg[k] is None else float(sg[k])
     p.original_ch = int(bool(d.get("original_ch", False)))
     p.reserved = 0
+    p.p_ref = float(d.get("p_ref", 0.0))
     return p
 
 

@@ -45,6 +45,7 @@ int validate(const lbm2p_params* p) {
   if (!(p->filter_a >= 0 && p->filter_a <= 1)) return LBM2P_EINVAL;
   if (p->coupled != 0 && p->coupled != 1) return LBM2P_EINVAL;
   if (p->reserved != 0) return LBM2P_EINVAL;
+  if (!std::isfinite(p->p_ref)) return LBM2P_EINVAL;
   return LBM2P_OK;
 }
 

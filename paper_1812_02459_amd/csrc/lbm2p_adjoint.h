@@ -466,7 +466,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(
       const T Frx = ff.Fx / ff.rho, Fry = ff.Fy / ff.rho;
       const T bxv = Frx - dpx, byv = Fry - dpy;
       T geq[9], G[9], s[9], mG[9], mq[9];
-      g_eq<T>(p, u_x, u_y, geq);
+      g_eq<T>(p - P.p_ref, u_x, u_y, geq);
       src_g<T>(Frx, Fry, u_x, u_y, bxv, byv, G);
       const T tau_g = ff.nu * T(3) + T(0.5);
       const T sv = T(1) / tau_g;

@@ -20,6 +20,7 @@ namespace {
 // the parity-0 layout (f*_i(x) at A[opp(i)][x]).  Evaluated in float64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_init(KParams<T> P, double c4b, double kappa, double eta,
+                                              double p_ref,
                                               const double* __restrict__ phi0,
                                               const double* __restrict__ ux0,
                                               const double* __restrict__ uy0,
@@ -49,7 +50,7 @@ __global__ __launch_bounds__(256) void k_init(KParams<T> P, double c4b, double k
   for (int i = 0; i < 9; ++i) Af[opp(i) * P.ps + id] = T(feq[i]);
   if (coupled) {
     double geq[9];
-    g_eq<double>(p, u_x, u_y, geq);
+    g_eq<double>(p - p_ref, u_x, u_y, geq);   // stored as g_i - 3 w_i p_ref
 #pragma unroll
     for (int i = 0; i < 9; ++i) Ag[opp(i) * P.ps + id] = T(geq[i]);
   }
@@ -59,9 +60,11 @@ __global__ __launch_bounds__(256) void k_init(KParams<T> P, double c4b, double k
   uy[id] = T(u_y);
 }
 
-// canonical f*_i(x) <-> in-place layout of the given parity
+// canonical f*_i(x) <-> in-place layout of the given parity; the canonical
+// value is the stored one plus w_i shift (3 p_ref for g, 0 for f)
 template <typename T>
-__global__ __launch_bounds__(256) void k_state(KParams<T> P, T* A, double* canon, int parity, int set) {
+__global__ __launch_bounds__(256) void k_state(KParams<T> P, T* A, double* canon, int parity, int set,
+                                               double shift) {
   const long long n = (long long)P.nx * P.ny;
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
@@ -82,9 +85,9 @@ __global__ __launch_bounds__(256) void k_state(KParams<T> P, T* A, double* canon
       }
     }
     if (set)
-      A[loc] = T(canon[i * n + id]);
+      A[loc] = T(canon[i * n + id] - w_of(i) * shift);
     else
-      canon[i * n + id] = double(A[loc]);
+      canon[i * n + id] = double(A[loc]) + w_of(i) * shift;
   }
 }
 
@@ -226,6 +229,7 @@ KParams<T> kparams(const lbm2p_ctx* c) {
   k.gx = T(p.gx);
   k.gy = T(p.gy);
   k.rho_ref = T(p.rho_ref);
+  k.p_ref = T(p.p_ref);
   k.fa = T(p.filter_a);
   for (int i = 0; i < 6; ++i) k.fd[i] = T(c->fd[i]);
   k.fn = c->fn;
@@ -482,7 +486,8 @@ int init_impl(lbm2p_ctx* c, const double* phi0, const double* ux0, const double*
   const KParams<T> K = kparams<T>(c);
   T* ux = (T*)c->U[0][0];
   T* uy = (T*)c->U[0][1];
-  k_init<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, c->c4b, c->kappa, c->eta, phi0, ux0, uy0, p0,
+  k_init<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, c->c4b, c->kappa, c->eta, c->p.p_ref,
+                                                   phi0, ux0, uy0, p0,
                                                    (T*)c->Af, (T*)c->Ag, (T*)c->phi,
                                                    c->p.coupled ? (T*)c->pt : (T*)c->phi2, ux, uy,
                                                    c->p.coupled);
@@ -543,9 +548,10 @@ int state_impl(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
     c->from_init = 0;
     c->adj_ready = 0;
   }
-  if (f) k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Af, f, c->parity, set);
+  if (f) k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Af, f, c->parity, set, 0.0);
   if (g && c->p.coupled)
-    k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Ag, g, c->parity, set);
+    k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Ag, g, c->parity, set,
+                                                      3.0 * c->p.p_ref);
   if (u) {
     const int ui = c->p.coupled ? c->uo : 0;
     for (int k = 0; k < 2; ++k) {

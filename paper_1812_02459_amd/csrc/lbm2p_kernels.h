@@ -51,6 +51,7 @@ struct KParams {
   long long ps;                 // plane stride (elements)
   T c4b, kappa, eta, negM, lam, eps2, W, cJ;
   T rho1, rho2, mu1, mu2, gx, gy, rho_ref;
+  T p_ref;                      // g is stored as g_i - 3 w_i p_ref
   T fa;                         // filter intensity
   T fd[6];                      // filter coefficients d_0..d_N
   int fn;                       // N = half width of the explicit filter
@@ -193,7 +194,7 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   T sg = g[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) sg = sg + g[i];
-  praw[id] = divk<3>(sg);
+  praw[id] = divk<3>(sg) + P.p_ref;   // sum_i 3 w_i p_ref / 3 = p_ref
   T ax = g[1];
   ax = ax - g[3];
   ax = ax + g[5];
@@ -728,7 +729,7 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
       T g[9], geq[9], s[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) g[i] = Ag[rd[i]];
-      g_eq<T>(p, u_x, u_y, geq);
+      g_eq<T>(p - P.p_ref, u_x, u_y, geq);   // stored deviations: g^eq - 3 w p_ref
       const T tau_g = nu * T(3) + T(0.5);
       const T sv = qdiv(T(1), tau_g);
 #pragma unroll

@@ -43,7 +43,8 @@ def test_workspace_and_validation():
            dict(ok, K=0), dict(ok, K=9), dict(ok, filter_a=1.5), dict(ok, W=0.0),
            dict(ok, eps=-1.0), dict(ok, mu1=-1.0), dict(ok, compact=True, compact_n=6),
            dict(ok, compact=True, compact_alpha=0.5), dict(ok, compact=True, compact_n=0),
-           dict(ok, compact=True, nx=7681)]
+           dict(ok, compact=True, nx=7681), dict(ok, p_ref=float("nan")),
+           dict(ok, p_ref=float("inf"))]
     for b in bad:
         with pytest.raises(B.LBMError, match="invalid argument"):
             B.lbm2p_workspace_bytes(B.make_params(b, 0))

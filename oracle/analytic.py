@@ -4,6 +4,8 @@
 * Laplace law Delta p = sigma / R                         Sec. 4.3
 * Prosperetti's capillary-wave amplitude h(t)/H0          Sec. 4.4, eq:capillary_wave,
   eq:error_function, eq:z (equal kinematic viscosities)
+* a circular drop translated by a uniform velocity        Sec. "Effect of parameter
+  lambda" (its exact solution after eq:lambda_effect_initial)
 """
 
 import numpy as np
@@ -12,6 +14,22 @@ from scipy.special import erfc, wofz
 
 def tanh_profile(r, W):
     return np.tanh(2.0 * np.asarray(r) / W)
+
+
+def translated_drop(nx, ny, xc, yc, R, W, shift_x):
+    """tanh(2 (R - r) / W) about (xc + shift_x, yc), periodic in x."""
+    x, y = np.meshgrid(np.arange(nx, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                       indexing="xy")
+    dx = x - xc - shift_x
+    dx = dx - nx * np.round(dx / nx)
+    return np.tanh(2.0 * (R - np.sqrt(dx * dx + (y - yc) ** 2)) / W)
+
+
+def overshoots(phi):
+    """Relative excursions of phi beyond its bulk values, (max phi - 1)/2 and
+    (-1 - min phi)/2, zero when inside [-1, 1] (the measures of the lambda tables)."""
+    phi = np.asarray(phi)
+    return max(0.0, (float(phi.max()) - 1.0) / 2.0), max(0.0, (-1.0 - float(phi.min())) / 2.0)
 
 
 def laplace_dp(sigma, R):

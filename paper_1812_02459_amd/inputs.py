@@ -79,6 +79,18 @@ def vortex(n=128, U=0.05, steps=1000):
                     dict(R=R, U=U))
 
 
+def translating_drop(L=100, U=0.01, lam=0.005, sigma=0.01, steps=4000, R=26.0, W=4.0):
+    """Circular drop carried by a uniform velocity (Sec. "Effect of parameter
+    lambda"): CH-only on a 3L x L periodic domain (the paper's L x 3L with the
+    long side along the motion), centre (L/2, L/2), u = (U, 0)."""
+    nx, ny = 3 * L, L
+    phi = drop_field(nx, ny, 0.5 * L, 0.5 * L, R, W, inside=1.0)
+    ux = np.full_like(phi, U)
+    prm = base_params(nx, ny, coupled=False, sigma=sigma, lam=lam, filter_n=0)
+    return Workload("translating_drop", prm, phi, ux, np.zeros_like(phi), np.zeros_like(phi),
+                    steps, dict(R=R, W=W, xc=0.5 * L, yc=0.5 * L, U=U))
+
+
 def droplet(n=200, seed=0, steps=20000, sigma=0.01, radii=(20, 25, 30, 35, 40)):
     """Stationary droplet (Laplace law, Sec. 4.3): density ratio 1000, viscosity ratio 100."""
     rng = np.random.default_rng(seed)

@@ -161,3 +161,50 @@ def test_fp32_deviation_storage_with_background_pressure():
     assert d64 <= 1e-12, d64
     assert e_shift <= 1e-4, e_shift
     assert e_shift * 10 <= e_plain, (e_shift, e_plain)
+
+
+# Relative maximum / minimum errors of phi from the paper's two lambda tables
+# (translating drop, Sec. "Effect of parameter lambda"), keyed (U, sigma), in
+# the order lambda = 0, 0.001, 0.005, 0.01, 0.05 (None: not reported).
+_LAMBDAS = (0.0, 0.001, 0.005, 0.01, 0.05)
+_PAPER_MAX = {(0.01, 1e-2): (0.06314, 0.01638, 0.00002, 0.0, 0.0),
+              (0.01, 1e-3): (0.13071, 0.01384, 0.0, 0.00004, None),
+              (0.01, 1e-4): (0.20146, 0.01708, 0.00254, 0.00168, None),
+              (0.05, 1e-2): (0.10459, 0.06907, 0.01356, 0.00005, 0.0),
+              (0.05, 1e-3): (0.19082, 0.09880, 0.01665, 0.00058, 0.00088),
+              (0.05, 1e-4): (0.21659, 0.10610, 0.01805, 0.00075, 0.00385)}
+
+
+def test_translating_drop_lambda_tables():
+    """The paper's translating drop at its size (L = 100: a 300 x 100 periodic
+    domain, R = 26, W = 4, 4000 steps), FP64, every (U, sigma, lambda) of its
+    two tables, printed beside the paper's maximum errors.  The paper's values
+    come from its own discretisation choices, several of which it leaves open
+    (the readings of this library), so the check is the trend they show: a
+    large overshoot of phi beyond +-1 without the profile correction (lambda = 0,
+    > 0.03 in every column), falling as lambda grows to 0.005, and at 0.01 no
+    more than the tiny deviation the paper reports there (its largest entry at
+    lambda = 0.01 is 0.00168; measured here <= 1.4e-4; the paper also notes
+    the error stops decreasing, and the first run of this check, which asked
+    for no rise from 0.005 to 0.01, read 7.9e-5 -> 1.3e-4)."""
+    from paper_1812_02459_amd.binding import Sim
+    rows = {}
+    for (U, sig), paper in _PAPER_MAX.items():
+        got = []
+        for lam in _LAMBDAS:
+            wl = I.translating_drop(L=100, U=U, lam=lam, sigma=sig, steps=4000)
+            sim = Sim(wl.params, precision=0)
+            sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
+            sim.step(wl.steps)
+            ph = sim.moments()["phi"].cpu().numpy()
+            sim.close()
+            got.append(A.overshoots(ph) if np.isfinite(ph).all() else (float("nan"),) * 2)
+        rows[(U, sig)] = got
+        print(f"U={U} sigma={sig}: lambda -> (max, min) overshoot, paper max:",
+              [(lam, "%.5f" % g[0], "%.5f" % g[1], p) for lam, g, p in zip(_LAMBDAS, got, paper)],
+              flush=True)
+    _record("translating_drop", {f"U={U},sigma={s}": v for (U, s), v in rows.items()})
+    for key, got in rows.items():
+        m = [max(g) for g in got]
+        assert m[0] > 0.03, (key, m)
+        assert m[0] > m[1] > m[2] and m[3] <= 0.00168, (key, m)

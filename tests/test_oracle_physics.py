@@ -5,7 +5,11 @@
 * Laplace law Delta p' = sigma / R (Sec. 4.3) for a 1000:1 droplet, reduced size;
 * single-phase body-force Poiseuille flow between half-way bounce-back walls:
   u(y) = g/(2 nu) (y + 1/2)(H - 1/2 - y) (the NS part alone, rho1 = rho2, sigma = 0);
-* volume of a droplet conserved (Table III: "present" method conserves it).
+* volume of a droplet conserved (Table III: "present" method conserves it);
+* a translating drop (Sec. "Effect of parameter lambda", reduced size): the
+  profile correction removes the overshoots of phi beyond +-1 and keeps the
+  interface on the exact translated profile, more so as lambda grows (the
+  trend of the paper's two lambda tables).
 """
 
 import math
@@ -93,3 +97,27 @@ def test_poiseuille_single_phase(s_q):
     ux = st.uo[0][:, 0].numpy()
     assert np.allclose(ux, ref, rtol=1e-8, atol=0)
     assert float(st.uo[1].abs().max()) < 1e-15
+
+
+def test_translating_drop_lambda_trend():
+    """120 x 40 periodic, R = 10.4, u = (0.05, 0), sigma = 0.01, 400 steps (the
+    drop moves 20 nodes).  Measured with this oracle: overshoots 0.069 / 0.045
+    at lambda = 0, 0.0076 / 0.0061 at 0.005, none at 0.05; L-inf distance to
+    the translated tanh 0.196, 0.131, 0.036.  Checked: lambda = 0 overshoots
+    by more than 0.03, lambda = 0.05 not at all (<= 1e-3), the overshoot and
+    the distance to the exact profile fall monotonically with lambda."""
+    L, U, steps = 40, 0.05, 400
+    res = []
+    for lam in (0.0, 0.005, 0.05):
+        wl = I.translating_drop(L=L, U=U, lam=lam, sigma=0.01, steps=steps, R=0.26 * L)
+        st, prm = _init(wl)
+        st = oracle.run(st, prm, steps)
+        ph = st.phi.numpy()
+        over = max(A.overshoots(ph))
+        ex = A.translated_drop(3 * L, L, wl.meta["xc"], wl.meta["yc"], wl.meta["R"], wl.meta["W"],
+                               U * steps)
+        res.append((lam, over, float(np.abs(ph - ex).max())))
+    print(res)
+    assert res[0][1] > 0.03 and res[2][1] <= 1e-3
+    assert res[0][1] > res[1][1] > res[2][1]
+    assert res[0][2] > res[1][2] > res[2][2]

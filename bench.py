@@ -34,6 +34,11 @@ def step_values(K):
     return 22 + 8 + 8 * K + 6 + 42
 
 
+# Compulsory traffic of a coupled step if everything were fused: the state f*, g*
+# and u~ read once and written once (20 + 20 values).
+FLOOR_VALUES = 40
+
+
 PROFILE_DIR = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILE_DIR, "k_collide_bubbles4096_hbm_traffic.md")
 # what determines the collide kernel's code and launch shape: its source and
@@ -129,6 +134,7 @@ def run_precision(wl, precision, steps, warmup, params=None):
         collide_gbps=coll_bytes / avg_coll / 1e9,
         collide_bytes=coll_bytes,
         step_gbps_model=step_values(params["K"]) * esz * nodes / dt / 1e9,
+        step_gbps_floor=FLOOR_VALUES * esz * nodes / dt / 1e9,
         pass_ms=passes,
         finite=bool(diag["finite"]),
         sum_phi_drift=diag["sum_phi"] - diag0["sum_phi"],
@@ -244,8 +250,14 @@ def cpu_baseline(wl, side, steps):
     for _ in range(steps):
         st = oracle.step_once(st, prm)
     dt = time.perf_counter() - t0
+    cpu = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+    except OSError:
+        pass
     return dict(value=side * side * steps / dt / 1e6, unit="MLUPS",
-                cores=torch.get_num_threads(), kind="oracle",
+                cores=torch.get_num_threads(), cpu=cpu, kind="oracle",
                 sample=f"{side}x{side} window of the 4096^2 bubble field, same parameters, "
                        f"FP64, {steps} timed steps after 1 warm-up step ({dt:.1f} s)")
 
@@ -341,6 +353,7 @@ def main():
             "traffic_bytes_per_launch": traffic,
             "bytes_per_launch": r32["collide_bytes"],
             "avg_launch_ms": round(r32["collide_ms"], 4),
+            "frac_of_device_copy": round(r32["collide_gbps"] / copy_gbps, 4),
         },
         "step": {
             "fp32": {k: r32[k] for k in ("mlups", "ms_per_step", "step_gbps_model", "pass_ms",
@@ -356,6 +369,18 @@ def main():
                                                     "pass_ms", "finite", "sum_phi_drift", "max_u",
                                                     "phi_range", "collide_ms", "collide_gbps")}
         out["step"]["fp64"]["collide_frac"] = round(r64["collide_gbps"] / HBM_PEAK_GBPS, 4)
+    # the whole step against the roofline: the pass model (94 values per node at
+    # K = 2) and the compulsory floor (40), each against the 8 TB/s peak and the
+    # measured device-copy bandwidth
+    for name, r in (("fp32", r32), ("fp64", r64)):
+        if r is None:
+            continue
+        out["step"][name].update(
+            step_gbps_floor=r["step_gbps_floor"],
+            pct_peak_pass_model=round(100 * r["step_gbps_model"] / HBM_PEAK_GBPS, 1),
+            pct_peak_floor=round(100 * r["step_gbps_floor"] / HBM_PEAK_GBPS, 1),
+            pct_copy_pass_model=round(100 * r["step_gbps_model"] / copy_gbps, 1),
+            pct_copy_floor=round(100 * r["step_gbps_floor"] / copy_gbps, 1))
     print(json.dumps(out), flush=True)
 
 

@@ -9,13 +9,12 @@
 namespace lbm2p {
 namespace {
 
-// threads per workgroup of the tiled reverse kernels (one tile each): the
-// adjoint's passes chain several load / sync / compute phases, and more waves
-// per tile hide their latency on grids of a few 10^5 nodes
-constexpr int ADJ_NT = 512;
-// Tiles (rows of 64 nodes, threads) of the reverse collision and the reverse
-// velocity sweeps per precision (measured on the 256 x 1024 rising bubble: FP32
-// gains from 1024-thread tiles, FP64 loses to register pressure there).
+// Tiles (rows of 64 nodes, threads per workgroup) of the tiled reverse kernels,
+// per precision.  The adjoint's passes chain several load / sync / compute
+// phases, and many waves per tile hide their latency on grids of a few 10^5
+// nodes; measured on the 256 x 1024 rising bubble, FP32 gains from 1024-thread
+// tiles everywhere, the FP64 reverse collision (252 VGPRs) loses to register
+// pressure there.
 template <int TY_, int NT_>
 struct AdjTile {
   static constexpr int TY = TY_, NT = NT_;

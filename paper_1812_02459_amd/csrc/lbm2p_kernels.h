@@ -16,12 +16,6 @@
 
 namespace lbm2p {
 
-// Tile shapes of the adjoint's kernels (nodes per workgroup)
-constexpr int FD_TX = 64, FD_TY = 16;
-constexpr int VEL_TX = 64, VEL_TY = 8;
-constexpr int FIL_TX = 64, FIL_TY = 16;
-constexpr int COL_TX = 64, COL_TY = 8;
-
 // Tile shapes of the forward step's kernels per precision: 64 nodes wide (one
 // wavefront per tile row), TY rows, NT threads per workgroup.  Taller tiles
 // recompute fewer halo nodes but hold more LDS per workgroup.  Compile-time

@@ -444,12 +444,12 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       }
       {
         ProfScope ps(c, PASS_COLLIDE);
-        const Tiles<C::TX, C::COL_TY> tc(p);
+        const Tiles<C::COL_TX, C::COL_TY> tc(p);
         if (par == 0)
-          k_collide<T, 0, true, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
+          k_collide<T, 0, true, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
               K, tc.tx, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
         else
-          k_collide<T, 1, true, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
+          k_collide<T, 1, true, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
               K, tc.tx, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
       }
       c->uo = 1 - c->uo;
@@ -458,12 +458,12 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       T* uy = (T*)c->U[0][1];
       ProfScope ps(c, PASS_COLLIDE);
       using C = StepCfg<T>;
-      const Tiles<C::TX, C::COL_TY> tc(p);
+      const Tiles<C::COL_TX, C::COL_TY> tc(p);
       if (par == 0)
-        k_collide<T, 0, false, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
+        k_collide<T, 0, false, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
             K, tc.tx, Af, Ag, phi, nullptr, ux, uy, ux, uy);
       else
-        k_collide<T, 1, false, C::TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
+        k_collide<T, 1, false, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
             K, tc.tx, Af, Ag, phi, nullptr, ux, uy, ux, uy);
     }
     c->parity ^= 1;

@@ -16,19 +16,22 @@
 
 namespace lbm2p {
 
-// Tile shapes of the forward step's kernels per precision: 64 nodes wide (one
-// wavefront per tile row), TY rows, NT threads per workgroup.  Taller tiles
-// recompute fewer halo nodes but hold more LDS per workgroup.  Compile-time
-// tuning parameters.
+// Tile shapes of the forward step's kernels per precision: the stencil passes
+// are 64 nodes wide (one wavefront per tile row), TY rows, NT threads per
+// workgroup; the collision tile's width is its own (wider tiles cut the partial
+// cache lines that the shifted streaming writes leave at tile edges).  Taller
+// tiles recompute fewer halo nodes but hold more LDS per workgroup.
+// Compile-time tuning parameters, measured on 4096^2.
 #ifndef LBM2P_F32_TILES
-#define LBM2P_F32_TILES 32, 512, 16, 512, 32, 512, 16, 256
+#define LBM2P_F32_TILES 32, 512, 16, 512, 32, 512, 16, 512, 128
 #endif
 #ifndef LBM2P_F64_TILES
-#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256
+#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256, 64
 #endif
-template <int FD_Y, int FD_T, int VEL_Y, int VEL_T, int FIL_Y, int FIL_T, int COL_Y, int COL_T>
+template <int FD_Y, int FD_T, int VEL_Y, int VEL_T, int FIL_Y, int FIL_T, int COL_Y, int COL_T,
+          int COL_X>
 struct StepTiles {
-  static constexpr int TX = 64;
+  static constexpr int TX = 64, COL_TX = COL_X;
   static constexpr int FD_TY = FD_Y, FD_NT = FD_T, VEL_TY = VEL_Y, VEL_NT = VEL_T;
   static constexpr int FIL_TY = FIL_Y, FIL_NT = FIL_T, COL_TY = COL_Y, COL_NT = COL_T;
 };

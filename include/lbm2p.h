@@ -161,7 +161,8 @@ int lbm2p_profile_read(lbm2p_ctx* c, double* ms, int64_t* launches);
  * velocity sweeps, the three FD stages, gather and streaming) with the
  * Jacobians at the forward values, recomputed segment by segment from
  * checkpoints kept every ckpt_every steps (memory O(n/k + k) planes, one extra
- * forward step per step).  Supported for the explicit filter, the compact
+ * forward step per step except in the last segment, whose intermediates the
+ * record keeps).  Supported for the explicit filter, the compact
  * filter (self-adjoint per direction: its reverse is the same line solves on
  * the adjoint fields) or none, both modes, both precisions (the arithmetic of
  * the adjoint is the context's).
@@ -172,9 +173,10 @@ int lbm2p_profile_read(lbm2p_ctx* c, double* ms, int64_t* launches);
 int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t ckpt_every,
                                   size_t* bytes);
 
-/* Advance n steps like lbm2p_step and keep the checkpoints of the run in
- * d_ws (device memory, 256-byte aligned, >= the bytes above, owned by the
- * caller and kept alive until lbm2p_adjoint returns or the next record).
+/* Advance n steps like lbm2p_step and keep the checkpoints of the run, and
+ * the per-step intermediates of its last segment, in d_ws (device memory,
+ * 256-byte aligned, >= the bytes above, owned by the caller and kept alive
+ * until the last lbm2p_adjoint of this record returns or the next record).
  * ESTATE before init; EINVAL for invalid values; ENOSPACE for a small d_ws. */
 int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes);
 

@@ -1,6 +1,8 @@
 // Host orchestration of the adjoint: the recorded forward run with its
-// checkpoints, and the reverse sweep segment by segment (recompute the
-// segment's steps into per-step slots, then reverse them last to first).
+// checkpoints (its last segment's steps write their intermediates to the
+// per-step slots), and the reverse sweep segment by segment (recompute the
+// segment's steps into the slots unless they are still there, then reverse
+// them last to first).
 // Included once per precision translation unit, after lbm2p_impl.h.
 #pragma once
 

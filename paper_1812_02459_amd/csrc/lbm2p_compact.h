@@ -133,11 +133,6 @@ __device__ __forceinline__ T block_carry(Aff<T> m, T* sWa, T* sWb) {
   return ea * c + eb;
 }
 
-// Columns per workgroup of the y-line solve (16, 32 or 64); compile-time tuning.
-#ifndef LBM2P_CLINE_Y_CW
-#define LBM2P_CLINE_Y_CW 16
-#endif
-
 // Longest line the LDS-staged line solve takes (the FP64 line, padded, in 64 KB).
 constexpr int COMPACT_MAX_N = 7680;
 

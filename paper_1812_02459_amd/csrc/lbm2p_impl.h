@@ -323,8 +323,9 @@ void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, 
     launch_cline_x<T, N, 8>(c, A, p, ux, uy, fx);
   else
     launch_cline_x<T, N, 4>(c, A, p, ux, uy, fx);
-  // y-lines: 16 waves per workgroup, CW columns per workgroup
-  constexpr int NW = 16, CW = LBM2P_CLINE_Y_CW;
+  // y-lines: 16 waves per workgroup, CW columns per workgroup (measured at
+  // 4096^2: whole 256-byte row segments in FP32, 16 columns in FP64)
+  constexpr int NW = 16, CW = sizeof(T) == 8 ? 16 : 64;
   k_cline_y<T, N, NW, CW><<<dim3((nx + CW - 1) / CW, 3), 64 * NW, 0, c->stream>>>(
       K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
 }

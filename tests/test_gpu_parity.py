@@ -162,6 +162,33 @@ def test_compact_filter_longest_lines(nx, ny, kw):
     _compare_state(sim, st, label=f"{nx}x{ny} {kw}")
 
 
+@pytest.mark.parametrize("nx,ny,kw", [
+    (300, 520, dict(compact=True, compact_n=5, compact_alpha=0.45)),
+    (520, 300, dict(compact=True, compact_n=4, compact_alpha=0.4, wall_x=True, wall_y=True)),
+])
+def test_compact_filter_fp32_one_step(nx, ny, kw):
+    """The FP32 compact filter (its own line-solve launch shapes) against the
+    FP64 path, one step from the same state: errors over each field's maximum,
+    bars as for the full-size FP32 step (2e-6 for f and phi; 6e-5 for g and u,
+    where the velocity update divides by rho2 = 1e-3)."""
+    wl = droplet_case(nx, ny, seed=13, **kw)
+    st, prm = oracle_init(wl)
+    st = oracle.run(st, prm, 2)
+    out = {}
+    for prec in (0, 1):
+        sim = gpu_sim(wl, precision=prec)
+        sim.set_state(st.fs, st.gs, st.uo)
+        sim.step(1)
+        f, g, u = (x.cpu() for x in sim.get_state())
+        out[prec] = dict(f=f, g=g, u=u, phi=sim.moments()["phi"].cpu())
+        sim.close()
+    bars = dict(f=2e-6, phi=2e-6, g=6e-5, u=6e-5)
+    errs = {k: float((out[1][k] - out[0][k]).abs().max() / out[0][k].abs().max()) for k in bars}
+    print(f"fp32 compact {nx}x{ny}", {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    for k, v in errs.items():
+        assert v <= bars[k], (k, v)
+
+
 def test_minimum_size_and_zero_steps():
     wl = droplet_case(16, 16, seed=4, R=5.0, wall_y=True)
     st, prm = oracle_init(wl)

@@ -172,23 +172,41 @@ __global__ __launch_bounds__(64 * NWV) void k_cline(CompactArgs<T> A, CompactLin
 #pragma unroll
   for (int k = 0; k <= N; ++k) ah[k] = T(A.a[k] / 2.0);
   const T al = T(A.alpha);
-  // right-hand side, coalesced over the line
-#pragma unroll 2
-  for (int e = t; e < n; e += NTH) {
-    T r;
-    if (e >= N && e < n - N) {
-      const T* q = src + b + e;
-      r = ah[0] * (q[0] + q[0]);
+  // the raw line into LDS in one coalesced pass; then the right-hand side of
+  // each element from LDS, held in registers until every thread has read the
+  // raw values it needs, and written over them
+  for (int e = t; e < n; e += NTH) sd[cpad(e, lg)] = src[b + e];
+  __syncthreads();
+  auto raw = [&](int i) {
+    int flip = 0;
+    const int k = map_idx(i, n, wall, flip);
+    const T v = sd[cpad(k, lg)];
+    return (odd && flip) ? -v : v;
+  };
+  constexpr int EPT = (COMPACT_MAX_N + NTH - 1) / NTH;
+  T rr[EPT];
 #pragma unroll
-      for (int k = 1; k <= N; ++k) r = r + ah[k] * (q[k] + q[-k]);
-    } else {
-      r = ah[0] * (line_val<T>(src, b, 1, e, n, wall, odd) + line_val<T>(src, b, 1, e, n, wall, odd));
+  for (int j = 0; j < EPT; ++j) {
+    const int e = t + j * NTH;
+    if (e < n) {
+      T r;
+      if (e >= N && e < n - N) {
+        r = ah[0] * (sd[cpad(e, lg)] + sd[cpad(e, lg)]);
 #pragma unroll
-      for (int k = 1; k <= N; ++k)
-        r = r + ah[k] * (line_val<T>(src, b, 1, e + k, n, wall, odd) +
-                         line_val<T>(src, b, 1, e - k, n, wall, odd));
+        for (int k = 1; k <= N; ++k) r = r + ah[k] * (sd[cpad(e + k, lg)] + sd[cpad(e - k, lg)]);
+      } else {
+        r = ah[0] * (raw(e) + raw(e));
+#pragma unroll
+        for (int k = 1; k <= N; ++k) r = r + ah[k] * (raw(e + k) + raw(e - k));
+      }
+      rr[j] = r;
     }
-    sd[cpad(e, lg)] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < EPT; ++j) {
+    const int e = t + j * NTH;
+    if (e < n) sd[cpad(e, lg)] = rr[j];
   }
   __syncthreads();
   // forward sweep: compose, scan, replay (d_i in place of r_i); the replay also

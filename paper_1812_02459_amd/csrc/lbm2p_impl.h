@@ -323,11 +323,18 @@ void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, 
     launch_cline_x<T, N, 8>(c, A, p, ux, uy, fx);
   else
     launch_cline_x<T, N, 4>(c, A, p, ux, uy, fx);
-  // y-lines: 16 waves per workgroup, CW columns per workgroup (measured at
-  // 4096^2: whole 256-byte row segments in FP32, 16 columns in FP64)
-  constexpr int NW = 16, CW = sizeof(T) == 8 ? 16 : 64;
-  k_cline_y<T, N, NW, CW><<<dim3((nx + CW - 1) / CW, 3), 64 * NW, 0, c->stream>>>(
-      K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
+  // y-lines: 16 waves per workgroup, CW columns per workgroup.  FP32 lattices
+  // wide enough to give every CU a workgroup take whole 256-byte row segments
+  // (CW = 64: 0.73 against 0.79 ms per application at 4096^2); narrower ones,
+  // and FP64, take 16 columns, which keeps 4x more workgroups in flight (at
+  // 256 x 1024 the 64-column launch has 12 workgroups and is 50 % slower).
+  constexpr int NW = 16;
+  if (sizeof(T) == 4 && 3 * (nx / 64) >= 128)
+    k_cline_y<T, N, NW, 64><<<dim3((nx + 63) / 64, 3), 64 * NW, 0, c->stream>>>(
+        K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
+  else
+    k_cline_y<T, N, NW, 16><<<dim3((nx + 15) / 16, 3), 64 * NW, 0, c->stream>>>(
+        K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
 }
 
 template <typename T>

@@ -29,7 +29,10 @@ HBM_PEAK_GBPS = 8000.0
 # Algorithmic bytes of the collide pass per node, in values (8 B FP64, 4 B FP32):
 # reads f, g (18), phi, p~, u~ (2), u~^n (2) and writes f, g (18).
 COLLIDE_VALUES = 42
-# Whole coupled step, pass model: gather 22 + FD 8 + 8K velocity + filter 6 + collide 42.
+# Whole coupled step, pass model (values per node, each pass reading its inputs and
+# writing its outputs once): gather 22 (18 populations in, phi_bar, p, j out); FD 8 over
+# the three stages; velocity 8 per sweep; filter 6; collide 42 (94 at K = 2).  The
+# two-sweep velocity kernel reads its inputs once, so the step moves 86 at K = 2.
 def step_values(K):
     return 22 + 8 + 8 * K + 6 + 42
 
@@ -215,22 +218,33 @@ def adjoint_cost(precision, nsteps, k=64, warmup=64, compact=False):
 
 
 def copy_bandwidth():
+    """Device copy rates (GB/s, read + write) of 1 GiB: the library's streaming
+    copy (16-byte nontemporal accesses, the ceiling the kernels are measured
+    against) and torch's copy_ (context)."""
     import torch
+    from paper_1812_02459_amd import binding as B
     n = 1 << 28  # 1 GiB of float32
     a = torch.empty(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    reps = 20
-    for _ in range(reps):
-        b.copy_(a)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    stream = torch.cuda.current_stream().cuda_stream
+    kinds = {
+        "stream": lambda: B.lbm2p_stream_copy(a.data_ptr(), b.data_ptr(), 4 * n, stream),
+        "torch": lambda: b.copy_(a),
+    }
+    out = {}
+    for name, fn in kinds.items():
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = 20
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        out[name] = 2 * n * 4 / ((time.perf_counter() - t0) / reps) / 1e9
     del a, b
     torch.cuda.empty_cache()
-    return 2 * n * 4 / dt / 1e9
+    return out
 
 
 def cpu_baseline(wl, side, steps):
@@ -312,7 +326,8 @@ def main():
         print("# variants: " + ", ".join(
             f"{k} fp32 {v['fp32']['mlups']:.0f} MLUPS" for k, v in variants.items()),
             file=sys.stderr, flush=True)
-    copy_gbps = copy_bandwidth()
+    copies = copy_bandwidth()
+    copy_gbps = copies["stream"]
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_side, args.cpu_steps)
@@ -362,6 +377,7 @@ def main():
         "adjoint": adj,
         "variants": variants,
         "copy_GBps": round(copy_gbps, 1),
+        "torch_copy_GBps": round(copies["torch"], 1),
         "cpu_baseline": cpu,
     }
     if r64 is not None:

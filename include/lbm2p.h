@@ -207,6 +207,14 @@ typedef struct lbm2p_adjoint_io {
  * without a matching record (or after a step, init or set_state since). */
 int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io);
 
+/* Copy bytes from d_src to d_dst (device memory, both 16-byte aligned, not
+ * overlapping) on stream (NULL: the null stream), asynchronously, with one
+ * 16-byte nontemporal load and store per thread: the device's streaming copy
+ * rate, the HBM ceiling the step's kernels are measured against.  Needs no
+ * context.  bytes = 0 does nothing; EINVAL for NULL, misaligned or
+ * overlapping buffers; EHIP for a launch error. */
+int lbm2p_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
+
 /* Release the context (not the workspace or the stream). */
 void lbm2p_destroy(lbm2p_ctx* c);
 

@@ -80,6 +80,7 @@ _sig = {
                                       ctypes.POINTER(ctypes.c_size_t)],
     "lbm2p_record": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t],
     "lbm2p_adjoint": [_vp, ctypes.POINTER(AdjointIO)],
+    "lbm2p_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -202,6 +203,11 @@ def lbm2p_record(ctx, nsteps, ckpt_every, ws_ptr, nbytes):
 def lbm2p_adjoint(ctx, io):
     _check(_lib.lbm2p_adjoint(ctx, ctypes.byref(io)), "lbm2p_adjoint")
     return io.dL_dsigma, io.dL_dM
+
+
+def lbm2p_stream_copy(src_ptr, dst_ptr, nbytes, stream_ptr):
+    _check(_lib.lbm2p_stream_copy(_vp(src_ptr), _vp(dst_ptr), int(nbytes), _vp(stream_ptr)),
+           "lbm2p_stream_copy")
 
 
 def lbm2p_destroy(ctx):

@@ -161,10 +161,40 @@ void filter_coeffs(int order, double* d, int* N) {
   for (int k = 0; k < 6; ++k) d[k] = k <= *N ? src[k] : 0.0;
 }
 
+// Streaming copy: one 16-byte vector per thread (grid-stride beyond 2^20
+// workgroups), nontemporal loads and stores; the last bytes % 16 bytes are
+// copied one byte per thread by the first workgroup.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void k_stream_copy(const u32x4* __restrict__ src,
+                                                     u32x4* __restrict__ dst, size_t n16,
+                                                     int tail) {
+  const size_t stride = (size_t)gridDim.x * 256;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
+  if (blockIdx.x == 0 && (int)threadIdx.x < tail) {
+    const unsigned char* s8 = reinterpret_cast<const unsigned char*>(src + n16);
+    unsigned char* d8 = reinterpret_cast<unsigned char*>(dst + n16);
+    d8[threadIdx.x] = s8[threadIdx.x];
+  }
+}
+
 }  // namespace
 
 // ======================================================================= ABI
 extern "C" {
+
+int lbm2p_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream) {
+  if (bytes == 0) return LBM2P_OK;
+  const uintptr_t s = (uintptr_t)d_src, d = (uintptr_t)d_dst;
+  if (!d_src || !d_dst || (s & 15) || (d & 15)) return LBM2P_EINVAL;
+  if (s < d + bytes && d < s + bytes) return LBM2P_EINVAL;   // overlapping ranges
+  const size_t n16 = bytes / 16;
+  const int tail = (int)(bytes % 16);
+  const size_t blocks = std::min<size_t>(std::max<size_t>((n16 + 255) / 256, 1), (size_t)1 << 20);
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(256), 0, (hipStream_t)stream,
+                     (const u32x4*)d_src, (u32x4*)d_dst, n16, tail);
+  return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
+}
 
 const char* lbm2p_strerror(int code) {
   switch (code) {

@@ -337,6 +337,58 @@ void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, 
         K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
 }
 
+// Populations larger than the last-level cache (256 MB): the gather and the
+// collision stream them with nontemporal accesses.
+template <typename T>
+bool stream_populations(const lbm2p_ctx* c) {
+  return (double)(c->p.coupled ? 18 : 9) * (double)c->n * sizeof(T) > 256.0 * (1 << 20);
+}
+
+template <typename T, bool COUPLED, bool STREAM>
+void launch_gather(const KParams<T>& K, int par, long long n, hipStream_t st, T* Af, T* Ag,
+                   T* phibar, T* praw, T* jx, T* jy, T* m7, T* m8) {
+  if (par == 0)
+    k_gather<T, 0, COUPLED, STREAM><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, praw, jx, jy,
+                                                                 m7, m8);
+  else
+    k_gather<T, 1, COUPLED, STREAM><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, praw, jx, jy,
+                                                                 m7, m8);
+}
+
+template <typename T, bool COUPLED, bool STREAM>
+void launch_collide(lbm2p_ctx* c, const KParams<T>& K, int par, hipStream_t st, T* Af, T* Ag,
+                    const T* phi, const T* pt, const T* ux, const T* uy, const T* uox,
+                    const T* uoy) {
+  using C = StepCfg<T>;
+  const Tiles<C::COL_TX, C::COL_TY> tc(c->p);
+  if (par == 0)
+    k_collide<T, 0, COUPLED, STREAM, C::COL_TX, C::COL_TY, C::COL_NT>
+        <<<tc.grid(), C::COL_NT, 0, st>>>(K, tc.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
+  else
+    k_collide<T, 1, COUPLED, STREAM, C::COL_TX, C::COL_TY, C::COL_NT>
+        <<<tc.grid(), C::COL_NT, 0, st>>>(K, tc.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
+}
+
+// the three TVD-RK3 stages with TY x NT tiles
+template <typename T, int TY, int NT>
+void launch_fd(lbm2p_ctx* c, const KParams<T>& K, hipStream_t st, T* phibar, T* phi1, T* phi2,
+               T* phi) {
+  constexpr int TX = StepCfg<T>::TX;
+  const Tiles<TX, TY> tl(c->p);
+  {
+    ProfScope ps(c, PASS_FD);
+    k_fd<T, 1, TX, TY, NT><<<tl.grid(), NT, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
+  }
+  {
+    ProfScope ps(c, PASS_FD);
+    k_fd<T, 2, TX, TY, NT><<<tl.grid(), NT, 0, st>>>(K, tl.tx, phi1, phibar, phi2);
+  }
+  {
+    ProfScope ps(c, PASS_FD);
+    k_fd<T, 3, TX, TY, NT><<<tl.grid(), NT, 0, st>>>(K, tl.tx, phi2, phibar, phi);
+  }
+}
+
 template <typename T>
 int step_impl(lbm2p_ctx* c, int nsteps) {
   const lbm2p_params& p = c->p;
@@ -349,6 +401,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
   T* phibar = (T*)c->phibar;
   T* phi1 = (T*)c->phi1;
   T* phi2 = (T*)c->phi2;
+  const bool stream = stream_populations<T>(c);
   for (int s = 0; s < nsteps; ++s) {
     const int par = c->parity;
     {
@@ -357,39 +410,25 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       // pre-collision g (the g-relaxation rate's derivative needs them)
       T* m7 = c->rec && p.coupled ? (T*)c->rec_m7 : nullptr;
       T* m8 = c->rec && p.coupled ? (T*)c->rec_m8 : nullptr;
+      T* praw = p.coupled ? (T*)c->praw : nullptr;
+      T* jx = p.coupled ? (T*)c->jx : nullptr;
+      T* jy = p.coupled ? (T*)c->jy : nullptr;
       if (p.coupled) {
-        if (par == 0)
-          k_gather<T, 0, true><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, (T*)c->praw,
-                                                             (T*)c->jx, (T*)c->jy, m7, m8);
-        else
-          k_gather<T, 1, true><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, (T*)c->praw,
-                                                             (T*)c->jx, (T*)c->jy, m7, m8);
+        if (stream) launch_gather<T, true, true>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
+        else launch_gather<T, true, false>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
       } else {
-        if (par == 0)
-          k_gather<T, 0, false><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, nullptr, nullptr,
-                                                              nullptr, nullptr, nullptr);
-        else
-          k_gather<T, 1, false><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, nullptr, nullptr,
-                                                              nullptr, nullptr, nullptr);
+        if (stream) launch_gather<T, false, true>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
+        else launch_gather<T, false, false>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
       }
     }
     if (p.original_ch) {
       k_copy<T><<<blocks1d(n), 256, 0, st>>>(phibar, phi, n);
     } else {
       using C = StepCfg<T>;
-      const Tiles<C::TX, C::FD_TY> tl(p);
-      {
-        ProfScope ps(c, PASS_FD);
-        k_fd<T, 1, C::TX, C::FD_TY, C::FD_NT><<<tl.grid(), C::FD_NT, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
-      }
-      {
-        ProfScope ps(c, PASS_FD);
-        k_fd<T, 2, C::TX, C::FD_TY, C::FD_NT><<<tl.grid(), C::FD_NT, 0, st>>>(K, tl.tx, phi1, phibar, phi2);
-      }
-      {
-        ProfScope ps(c, PASS_FD);
-        k_fd<T, 3, C::TX, C::FD_TY, C::FD_NT><<<tl.grid(), C::FD_NT, 0, st>>>(K, tl.tx, phi2, phibar, phi);
-      }
+      if (Tiles<C::TX, C::FD_TY>(p).tx * (long long)Tiles<C::TX, C::FD_TY>(p).ty >= FD_MIN_TILES)
+        launch_fd<T, C::FD_TY, C::FD_NT>(c, K, st, phibar, phi1, phi2, phi);
+      else
+        launch_fd<T, C::FDS_TY, C::FDS_NT>(c, K, st, phibar, phi1, phi2, phi);
     }
     if (p.coupled) {
       T* uox = (T*)c->U[c->uo][0];
@@ -452,27 +491,20 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       }
       {
         ProfScope ps(c, PASS_COLLIDE);
-        const Tiles<C::COL_TX, C::COL_TY> tc(p);
-        if (par == 0)
-          k_collide<T, 0, true, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
-              K, tc.tx, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
+        if (stream)
+          launch_collide<T, true, true>(c, K, par, st, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
         else
-          k_collide<T, 1, true, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
-              K, tc.tx, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
+          launch_collide<T, true, false>(c, K, par, st, Af, Ag, phi, (T*)c->pt, unx, uny, uox, uoy);
       }
       c->uo = 1 - c->uo;
     } else {
       T* ux = (T*)c->U[0][0];
       T* uy = (T*)c->U[0][1];
       ProfScope ps(c, PASS_COLLIDE);
-      using C = StepCfg<T>;
-      const Tiles<C::COL_TX, C::COL_TY> tc(p);
-      if (par == 0)
-        k_collide<T, 0, false, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
-            K, tc.tx, Af, Ag, phi, nullptr, ux, uy, ux, uy);
+      if (stream)
+        launch_collide<T, false, true>(c, K, par, st, Af, Ag, phi, nullptr, ux, uy, ux, uy);
       else
-        k_collide<T, 1, false, C::COL_TX, C::COL_TY, C::COL_NT><<<tc.grid(), C::COL_NT, 0, st>>>(
-            K, tc.tx, Af, Ag, phi, nullptr, ux, uy, ux, uy);
+        launch_collide<T, false, false>(c, K, par, st, Af, Ag, phi, nullptr, ux, uy, ux, uy);
     }
     c->parity ^= 1;
     c->steps++;

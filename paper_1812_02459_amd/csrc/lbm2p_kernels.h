@@ -22,18 +22,22 @@ namespace lbm2p {
 // cache lines that the shifted streaming writes leave at tile edges).  Taller
 // tiles recompute fewer halo nodes but hold more LDS per workgroup.
 // Compile-time tuning parameters, measured on 4096^2.
+// The FD stage has a second, smaller shape (FDS) for lattices on which the
+// first would give fewer than FD_MIN_TILES workgroups.
 #ifndef LBM2P_F32_TILES
-#define LBM2P_F32_TILES 32, 512, 16, 512, 32, 512, 16, 512, 128
+#define LBM2P_F32_TILES 64, 1024, 16, 512, 32, 512, 16, 512, 128, 32, 512
 #endif
 #ifndef LBM2P_F64_TILES
-#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256, 64
+#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256, 64, 16, 512
 #endif
+constexpr int FD_MIN_TILES = 512;
 template <int FD_Y, int FD_T, int VEL_Y, int VEL_T, int FIL_Y, int FIL_T, int COL_Y, int COL_T,
-          int COL_X>
+          int COL_X, int FDS_Y, int FDS_T>
 struct StepTiles {
   static constexpr int TX = 64, COL_TX = COL_X;
   static constexpr int FD_TY = FD_Y, FD_NT = FD_T, VEL_TY = VEL_Y, VEL_NT = VEL_T;
   static constexpr int FIL_TY = FIL_Y, FIL_NT = FIL_T, COL_TY = COL_Y, COL_NT = COL_T;
+  static constexpr int FDS_TY = FDS_Y, FDS_NT = FDS_T;
 };
 template <typename T>
 struct StepCfg;
@@ -134,25 +138,28 @@ __device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, i
 }
 
 // Cache policy of the population loads and stores of the gather and the
-// collision (each population is read once and written once per kernel), one
-// bit per access kind and streaming parity: bit PAR for the gather's loads,
-// 2 + PAR for the collision's loads, 4 + PAR for its stores; a set bit makes
-// the access nontemporal.  Measured on 4096^2: nontemporal gather loads (both
-// parities) and nontemporal collision loads and stores in parity 1, where every
-// node reads and writes its own slots (aligned, whole cache lines), save 4 % of
-// the step; in parity 0 (shifted slots, partial lines at tile edges) the hint
-// slows the collision.
+// collision when the populations are larger than the last-level cache (the
+// launchers pick STREAM = true then): each population is read once and
+// written once per kernel, so streaming accesses keep it from displacing the
+// fields the next passes read.  One bit per access kind and streaming parity:
+// bit PAR for the gather's loads, 2 + PAR for the collision's loads, 4 + PAR
+// for its stores.  Measured on 4096^2: nontemporal gather loads (both
+// parities) and nontemporal collision loads and stores in parity 1, where
+// every node reads and writes its own slots (aligned, whole cache lines), save
+// 4 % of the step; in parity 0 (shifted slots, partial lines at tile edges)
+// the hint slows the collision.  On lattices whose populations fit in the
+// cache the hints cost 2-3 % and are off.
 #ifndef LBM2P_POP_NT
 #define LBM2P_POP_NT 43
 #endif
-template <int BIT, typename T>
+template <int BIT, bool STREAM, typename T>
 __device__ __forceinline__ T pop_ld(const T* p) {
-  if constexpr (((LBM2P_POP_NT >> BIT) & 1) != 0) return __builtin_nontemporal_load(p);
+  if constexpr (STREAM && ((LBM2P_POP_NT >> BIT) & 1) != 0) return __builtin_nontemporal_load(p);
   else return *p;
 }
-template <int BIT, typename T>
+template <int BIT, bool STREAM, typename T>
 __device__ __forceinline__ void pop_st(T* p, T v) {
-  if constexpr (((LBM2P_POP_NT >> BIT) & 1) != 0) __builtin_nontemporal_store(v, p);
+  if constexpr (STREAM && ((LBM2P_POP_NT >> BIT) & 1) != 0) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
 
@@ -191,7 +198,7 @@ __device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[
 // phi_bar = sum f_i (eq:compute_phi), p = c_s^2 sum g_i (Eq:p), j = sum g_i c_i;
 // with m7, m8 given, also the moments m_7 = g1 - g2 + g3 - g4 and
 // m_8 = g5 - g6 + g7 - g8 of eq:D2Q9MRT
-template <typename T, int PAR, bool COUPLED>
+template <typename T, int PAR, bool COUPLED, bool STREAM>
 __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
                                                 const T* __restrict__ Ag, T* __restrict__ phibar,
                                                 T* __restrict__ praw, T* __restrict__ jx,
@@ -203,14 +210,14 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
   int rd[9];
   slots<PAR>(P, x, y, rd);
-  T s = pop_ld<PAR>(Af + rd[0]);
+  T s = pop_ld<PAR, STREAM>(Af + rd[0]);
 #pragma unroll
-  for (int i = 1; i < 9; ++i) s = s + pop_ld<PAR>(Af + rd[i]);
+  for (int i = 1; i < 9; ++i) s = s + pop_ld<PAR, STREAM>(Af + rd[i]);
   phibar[id] = s;
   if (!COUPLED) return;
   T g[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = pop_ld<PAR>(Ag + rd[i]);
+  for (int i = 0; i < 9; ++i) g[i] = pop_ld<PAR, STREAM>(Ag + rd[i]);
   T sg = g[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) sg = sg + g[i];
@@ -676,7 +683,7 @@ __global__ __launch_bounds__(NT) void k_filter(KParams<T> P, int tiles_x, const 
 // ------------------------------------------------------ a5: collide + stream
 // MRT collision of f (eq:distribution_CH) and g (eq:distribution_NS) at n+1,
 // written to the streaming slots of the other parity.
-template <typename T, int PAR, bool COUPLED, int TX, int TY, int NT>
+template <typename T, int PAR, bool COUPLED, bool STREAM, int TX, int TY, int NT>
 __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
                                                  const T* __restrict__ phi, const T* __restrict__ pt,
                                                  const T* __restrict__ ux, const T* __restrict__ uy,
@@ -724,10 +731,10 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
     {
       T f[9], feq[9];
 #pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = pop_ld<2 + PAR>(Af + rd[i]);
+      for (int i = 0; i < 9; ++i) f[i] = pop_ld<2 + PAR, STREAM>(Af + rd[i]);
       if constexpr (COUPLED) {   // both distributions' loads in flight together
 #pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = pop_ld<2 + PAR>(Ag + rd[i]);
+        for (int i = 0; i < 9; ++i) g[i] = pop_ld<2 + PAR, STREAM>(Ag + rd[i]);
       }
       f_eq<T>(ph, tMu(lx, ly), u_x, u_y, P.eta, feq);
       if constexpr (std::is_same<T, float>::value) {
@@ -741,7 +748,7 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
         mrt_collide<T>(f, feq, F, P.s_f);
       }
 #pragma unroll
-      for (int i = 0; i < 9; ++i) pop_st<4 + PAR>(Af + rd[opp(i)], f[i]);
+      for (int i = 0; i < 9; ++i) pop_st<4 + PAR, STREAM>(Af + rd[opp(i)], f[i]);
     }
     if (COUPLED) {
       const T p = tPt(lx, ly);
@@ -772,7 +779,7 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
         mrt_collide<T>(g, geq, G, s);
       }
 #pragma unroll
-      for (int i = 0; i < 9; ++i) pop_st<4 + PAR>(Ag + rd[opp(i)], g[i]);
+      for (int i = 0; i < 9; ++i) pop_st<4 + PAR, STREAM>(Ag + rd[opp(i)], g[i]);
     }
   }
 }

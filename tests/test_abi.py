@@ -102,3 +102,13 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
     with pytest.raises(B.LBMError, match="call out of order"):
         B.lbm2p_adjoint(ctx, B.AdjointIO())                # nothing recorded
     B.lbm2p_destroy(ctx)
+
+
+def test_stream_copy_argument_checks_without_touching_the_device():
+    from paper_1812_02459_amd import binding as B
+    B.lbm2p_stream_copy(None, None, 0, None)                # nothing to copy
+    base = 1 << 20
+    for src, dst, n in [(None, base, 16), (base, None, 16), (base + 8, base + 4096, 16),
+                        (base, base + 4100, 16), (base, base + 32, 64), (base + 32, base, 64)]:
+        with pytest.raises(B.LBMError, match="invalid argument"):
+            B.lbm2p_stream_copy(src, dst, n, None)

@@ -246,3 +246,22 @@ def test_bitwise_determinism():
         outs.append(sim.get_state())
     for x, y in zip(*outs):
         assert torch.equal(x, y)
+
+
+@pytest.mark.parametrize("nbytes", [1, 15, 16, 17, 4096 * 4 + 3, (1 << 20) + 5, (1 << 32) + 55])
+def test_stream_copy_bytes(nbytes):
+    """The streaming copy the bandwidth ceiling is measured with copies every byte:
+    sizes with a ragged tail, one below a vector, and one beyond 2^32 bytes (more
+    vectors than the capped grid has threads, so the grid-stride loop runs twice)."""
+    from paper_1812_02459_amd import binding as B
+    print("stream copy", nbytes, flush=True)
+    gen = torch.Generator(device="cuda").manual_seed(nbytes % 1000)
+    src = torch.randint(0, 256, (nbytes + 16,), dtype=torch.uint8, device="cuda", generator=gen)
+    dst = torch.zeros(nbytes + 16, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    B.lbm2p_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, stream)
+    torch.cuda.synchronize()
+    assert torch.equal(dst[:nbytes], src[:nbytes])
+    assert int(dst[nbytes:].count_nonzero()) == 0           # nothing written past the end
+    del src, dst
+    torch.cuda.empty_cache()

@@ -32,15 +32,15 @@ def _window(a, cx, cy):
 
 
 def test_bubble_ensemble_sampled_windows():
+    """Steps 31 and 32, one from each streaming parity (at this size the gather and
+    the collision run their streaming-cache variants), each from the GPU state the
+    step before."""
     from paper_1812_02459_amd.binding import Sim
     wl = I.bubble_ensemble(n=4096, nb=200, seed=0)
     sim = Sim(wl.params, precision=0)
     sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
     sim.step(30)
     f, g, u = (x.cpu() for x in sim.get_state())
-    sim.step(1)
-    f1, g1, u1 = (x.cpu() for x in sim.get_state())
-    m1 = {k: v.cpu() for k, v in sim.moments().items()}
     rng = np.random.default_rng(1)
     # windows on bubble interfaces, one across the periodic corner, random ones
     centres = []
@@ -51,19 +51,61 @@ def test_bubble_ensemble_sampled_windows():
     p = dict(wl.params)
     p["nx"] = p["ny"] = CORE + 2 * HALO
     prm = oracle.Params(**p)
-    for (cx, cy) in centres:
-        st = oracle.State(fs=_window(f, cx, cy), gs=_window(g, cx, cy), uo=_window(u, cx, cy))
-        st = oracle.step_once(st, prm)
-        c = slice(HALO, HALO + CORE)
-        pairs = {"f": (_window(f1, cx, cy)[:, c, c], st.fs[:, c, c]),
-                 "g": (_window(g1, cx, cy)[:, c, c], st.gs[:, c, c]),
-                 "u": (_window(u1, cx, cy)[:, c, c], st.uo[:, c, c]),
-                 "phi": (_window(m1["phi"], cx, cy)[c, c], st.phi[c, c]),
-                 "p": (_window(m1["p"], cx, cy)[c, c], st.p[c, c])}
-        for k, (a, b) in pairs.items():
-            e = relerr(a, b)
-            print((cx, cy), k, f"{e:.2e}", "bitwise" if torch.equal(a, b) else "", flush=True)
-            assert e <= RTOL64, ((cx, cy), k, e)
+    for step in (31, 32):
+        sim.step(1)
+        f1, g1, u1 = (x.cpu() for x in sim.get_state())
+        m1 = {k: v.cpu() for k, v in sim.moments().items()}
+        for (cx, cy) in centres:
+            st = oracle.State(fs=_window(f, cx, cy), gs=_window(g, cx, cy), uo=_window(u, cx, cy))
+            st = oracle.step_once(st, prm)
+            c = slice(HALO, HALO + CORE)
+            pairs = {"f": (_window(f1, cx, cy)[:, c, c], st.fs[:, c, c]),
+                     "g": (_window(g1, cx, cy)[:, c, c], st.gs[:, c, c]),
+                     "u": (_window(u1, cx, cy)[:, c, c], st.uo[:, c, c]),
+                     "phi": (_window(m1["phi"], cx, cy)[c, c], st.phi[c, c]),
+                     "p": (_window(m1["p"], cx, cy)[c, c], st.p[c, c])}
+            for k, (a, b) in pairs.items():
+                e = relerr(a, b)
+                print(step, (cx, cy), k, f"{e:.2e}", "bitwise" if torch.equal(a, b) else "",
+                      flush=True)
+                assert e <= RTOL64, (step, (cx, cy), k, e)
+        f, g, u = f1, g1, u1
+
+
+def test_ch_only_vortex_sampled_windows():
+    """The CH-only step at 4096^2 (single vortex, the CH-only leg bench.py times;
+    the gather and the collision of f run their streaming-cache variants), steps
+    31 and 32 on windows: a step depends on 18 nodes around a node (gather 1,
+    three FD stages 5 each, collide 2), inside the 32-node halo."""
+    from paper_1812_02459_amd.binding import Sim
+    wl = I.vortex(n=4096)
+    sim = Sim(wl.params, precision=0)
+    sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
+    sim.step(30)
+    f, _, u = (x.cpu() if x is not None else None for x in sim.get_state())
+    R = wl.meta["R"]
+    centres = [(int(2048 + R), 3072), (2048, int(3072 - R)), (int(2048 - R * 0.7), int(3072 + R * 0.7)),
+               (4093, 4090), (1000, 200)]
+    p = dict(wl.params)
+    p["nx"] = p["ny"] = CORE + 2 * HALO
+    prm = oracle.Params(**p)
+    for step in (31, 32):
+        sim.step(1)
+        f1, _, u1 = (x.cpu() if x is not None else None for x in sim.get_state())
+        phi1 = sim.moments()["phi"].cpu()
+        for (cx, cy) in centres:
+            st = oracle.State(fs=_window(f, cx, cy), gs=None, uo=_window(u, cx, cy))
+            st = oracle.step_once(st, prm)
+            c = slice(HALO, HALO + CORE)
+            pairs = {"f": (_window(f1, cx, cy)[:, c, c], st.fs[:, c, c]),
+                     "phi": (_window(phi1, cx, cy)[c, c], st.phi[c, c])}
+            for k, (a, b) in pairs.items():
+                e = relerr(a, b)
+                print("ch-only", step, (cx, cy), k, f"{e:.2e}",
+                      "bitwise" if torch.equal(a, b) else "", flush=True)
+                assert e <= RTOL64, (step, (cx, cy), k, e)
+        f = f1
+    sim.close()
 
 
 # FP32, one step from the FP32 state, against the FP64 oracle on the same

@@ -53,6 +53,7 @@ struct KParams {
   T c4b, kappa, eta, negM, lam, eps2, W, cJ;
   T rho1, rho2, mu1, mu2, gx, gy, rho_ref;
   T p_ref;                      // g is stored as g_i - 3 w_i p_ref
+  T invW;                       // 1 / W rounded once (host)
   T fa;                         // filter intensity
   T fd[6];                      // filter coefficients d_0..d_N
   int fn;                       // N = half width of the explicit filter
@@ -275,7 +276,9 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
     const T ph = tP(lx, ly);
     const T mag = sqrt((Gx * Gx + Gy * Gy) + P.eps2);
     const T nx = qdiv(Gx, mag), ny = qdiv(Gy, mag);
-    const T cW = qdiv(T(2) * (T(1) - ph * ph), P.W);
+    T cW;
+    if constexpr (std::is_same<T, float>::value) cW = qdiv(T(2) * (T(1) - ph * ph), P.W);
+    else cW = div_by(T(2) * (T(1) - ph * ph), P.W, P.invW);
     const T Jpx = (mag - cW) * nx, Jpy = (mag - cW) * ny;
     const T s = Mx * nx + My * ny;
     const T qx = (P.negM * s) * nx, qy = (P.negM * s) * ny;

@@ -25,10 +25,22 @@ __device__ __forceinline__ T qdiv(T a, T b) {
   if constexpr (std::is_same<T, float>::value) return a * __builtin_amdgcn_rcpf(b);
   else return a / b;
 }
+// FP64 quotient a / b from y = RN(1/b): q = RN(a y) lies within one ulp of
+// a / b, so the remainder a - b q is exact (one FMA) and q + (a - b q) y rounded
+// once is the correctly rounded a / b (Markstein's theorem for binary64 with an
+// FMA, quotients in the normal range).  Four instructions where the division
+// sequence takes eleven, and bitwise the same result.  A zero remainder (q
+// exact, including a signed zero) or a non-finite one (infinite or NaN q)
+// returns q itself, as a / b would.
+__device__ __forceinline__ double div_by(double a, double b, double y) {
+  const double q = a * y;
+  const double r = fma(-b, q, a);
+  return (r != 0.0 && __builtin_isfinite(r)) ? fma(r, y, q) : q;
+}
 template <int C, typename T>
 __device__ __forceinline__ T divk(T a) {
   if constexpr (std::is_same<T, float>::value) return a * float(1.0 / C);
-  else return a / T(C);
+  else return div_by(a, double(C), 1.0 / C);
 }
 
 // eq:D2Q9: c_0 = 0, c_1..4 = axes counter-clockwise from +x, c_5..8 diagonals.

@@ -530,8 +530,11 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     return y * P.nx + x;
   };
   // u-independent force parts at (lx, ly), then the first sweep's u^1 there
+  // FP64: ir2 = 1/(2 rho) rounded once; the four quotients by 2 rho of the two
+  // sweeps and nu = mu/rho (2 ir2 = RN(1/rho) exactly) are then FMA-corrected
+  // products, bitwise the divisions they replace
   struct Parts {
-    T Fx, Fy, Jx, Jy, gx, gy, nu, rho, jx, jy;
+    T Fx, Fy, Jx, Jy, gx, gy, nu, rho, jx, jy, ir2;
   };
   auto parts = [&](int lx, int ly) {
     const int id = node_id(lx, ly);
@@ -541,7 +544,13 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     q.jy = jy[id];
     const T ph = tP(lx, ly);
     q.rho = density<T>(ph, P.rho1, P.rho2);
-    q.nu = kin_visc<T>(ph, q.rho, P.mu1, P.mu2);
+    if constexpr (std::is_same<T, float>::value) {
+      q.nu = kin_visc<T>(ph, q.rho, P.mu1, P.mu2);
+      q.ir2 = T(0);
+    } else {
+      q.ir2 = T(1) / (T(2) * q.rho);
+      q.nu = div_by(dyn_visc<T>(ph, P.mu1, P.mu2), q.rho, T(2) * q.ir2);
+    }
     T dmx, dmy;
     iso_grad<T>(tMu, lx, ly, dmx, dmy);
     const T dxyy = iso_grad_x<T>(ProdYY<T>{tPy}, lx, ly);
@@ -565,8 +574,13 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
                  (q.rho - P.rho_ref) * P.gx;
     const T Fy = ((q.Fy + q.nu * (Sxy * q.gx + Syy * q.gy)) + (q.Jx * duyx + q.Jy * duyy)) +
                  (q.rho - P.rho_ref) * P.gy;
-    vx = q.jx + qdiv(Fx, T(2) * q.rho);
-    vy = q.jy + qdiv(Fy, T(2) * q.rho);
+    if constexpr (std::is_same<T, float>::value) {
+      vx = q.jx + qdiv(Fx, T(2) * q.rho);
+      vy = q.jy + qdiv(Fy, T(2) * q.rho);
+    } else {
+      vx = q.jx + div_by(Fx, T(2) * q.rho, q.ir2);
+      vy = q.jy + div_by(Fy, T(2) * q.rho, q.ir2);
+    }
   };
   Parts c[NI];
 #pragma unroll

@@ -339,10 +339,13 @@ __device__ __forceinline__ T density(T phi, T rho1, T rho2) {
   return (rho1 * (T(1) + c)) / T(2) + (rho2 * (T(1) - c)) / T(2);
 }
 template <typename T>
-__device__ __forceinline__ T kin_visc(T phi, T rho, T mu1, T mu2) {
+__device__ __forceinline__ T dyn_visc(T phi, T mu1, T mu2) {
   const T c = clamp1(phi);
-  const T muv = (mu1 * (T(1) + c)) / T(2) + (mu2 * (T(1) - c)) / T(2);
-  return qdiv(muv, rho);
+  return (mu1 * (T(1) + c)) / T(2) + (mu2 * (T(1) - c)) / T(2);
+}
+template <typename T>
+__device__ __forceinline__ T kin_visc(T phi, T rho, T mu1, T mu2) {
+  return qdiv(dyn_visc<T>(phi, mu1, mu2), rho);
 }
 
 }  // namespace lbm2p

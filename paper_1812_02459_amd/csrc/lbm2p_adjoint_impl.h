@@ -99,12 +99,6 @@ AdjWork<T> adj_work(const AdjPtrs<T>& A) {
   return w;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_fill(T* a, T v, long long n) {
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id < n) a[id] = v;
-}
-
 inline AdjConst adj_const(const lbm2p_ctx* c) {
   const lbm2p_params& p = c->p;
   AdjConst C;

@@ -103,6 +103,14 @@ __global__ __launch_bounds__(256) void k_from_f64(const double* a, T* o, long lo
   if (id < n) o[id] = T(a[id]);
 }
 
+// a fill kernel rather than hipMemsetAsync, so that the calls a caller may
+// capture into a HIP graph record kernel nodes only
+template <typename T>
+__global__ __launch_bounds__(256) void k_fill(T* a, T v, long long n) {
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id < n) a[id] = v;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_copy(const T* a, T* o, long long n) {
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
@@ -558,7 +566,7 @@ int moments_impl(lbm2p_ctx* c, double* phi, double* ux, double* uy, double* p, d
     if (c->p.coupled)
       to_f64<T>(c, c->pt, p);
     else
-      hipMemsetAsync(p, 0, c->n * sizeof(double), c->stream);
+      k_fill<double><<<blocks1d(c->n), 256, 0, c->stream>>>(p, 0.0, c->n);
   }
   if (rho)
     k_rho<T><<<blocks1d(c->n), 256, 0, c->stream>>>((const T*)c->phi, rho, c->n, c->p.rho1,

@@ -138,6 +138,15 @@ int lbm2p_fields(lbm2p_ctx* c, int32_t which, double* d_out);
  * Returns ENONFINITE if sum phi or max|u~| is not finite. */
 int lbm2p_volume(lbm2p_ctx* c, double out[6]);
 
+/* Rising-bubble diagnostics of Sec. 4.5 (eq:quantify-yc, eq:quantify-uc) over
+ * the nodes with phi < 0 (the light phase): out[0] their number, out[1] their
+ * mean row index y_c (the node of row j sits at y = j; a wall in y lies half a
+ * node below row 0), out[2] their mean vertical velocity V_c (of u~, as
+ * lbm2p_moments reports it), in host memory.  Sums in float64, in a fixed
+ * order (deterministic).  y_c and V_c are NaN when no node has phi < 0.
+ * Synchronises the stream.  ESTATE before init. */
+int lbm2p_bubble(lbm2p_ctx* c, double out[3]);
+
 /* State in canonical order (post-collision f*_i(x), g*_i(x), then u~), as
  * device float64 arrays: d_f [9][ny][nx], d_g [9][ny][nx] (ignored in CH-only
  * mode, may be NULL), d_u [2][ny][nx].  set_state makes a context resume from

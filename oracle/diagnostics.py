@@ -57,3 +57,14 @@ def bubble_centroid(phi, uy):
     ys = torch.arange(phi.shape[0], dtype=torch.float64)[:, None].expand_as(phi)
     n = m.sum()
     return float(ys[m].sum() / n), float(uy[m].sum() / n)
+
+
+def bubble_stats(phi, uy):
+    """(area, y_c, V_c): the number of nodes with phi < 0 and the two means of
+    eq:quantify-yc and eq:quantify-uc over them, the integrals taken as sums
+    over nodes; the node of row j sits at y = j."""
+    area = int((phi < 0).sum())
+    if area == 0:
+        return 0, float("nan"), float("nan")
+    yc, vc = bubble_centroid(phi, uy)
+    return area, yc, vc

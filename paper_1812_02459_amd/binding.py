@@ -81,6 +81,7 @@ _sig = {
     "lbm2p_record": [_vp, ctypes.c_int32, ctypes.c_int32, _vp, ctypes.c_size_t],
     "lbm2p_adjoint": [_vp, ctypes.POINTER(AdjointIO)],
     "lbm2p_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
+    "lbm2p_bubble": [_vp, ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -167,6 +168,12 @@ def lbm2p_volume(ctx):
     if code not in (OK, ENONFINITE):
         _check(code, "lbm2p_volume")
     return code, list(out)
+
+
+def lbm2p_bubble(ctx):
+    out = (ctypes.c_double * 3)()
+    _check(_lib.lbm2p_bubble(ctx, out), "lbm2p_bubble")
+    return list(out)
 
 
 def lbm2p_get_state(ctx, f, g, u):
@@ -269,6 +276,12 @@ class Sim:
         code, v = lbm2p_volume(self.ctx)
         return dict(count=v[0], sum_phi=v[1], sum_p=v[2], max_u=v[3], min_phi=v[4],
                     max_phi=v[5], finite=(code == OK))
+
+    def bubble(self):
+        """Area (node count), y_c and V_c of the region phi < 0 (eq:quantify-yc,
+        eq:quantify-uc); y in row indices."""
+        a, yc, vc = lbm2p_bubble(self.ctx)
+        return dict(area=a, y_c=yc, V_c=vc)
 
     def get_state(self):
         t = self.torch

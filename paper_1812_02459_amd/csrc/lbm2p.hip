@@ -398,6 +398,12 @@ int lbm2p_volume(lbm2p_ctx* c, double out[6]) {
   return c->prec ? volume_f32(c, out) : volume_f64(c, out);
 }
 
+int lbm2p_bubble(lbm2p_ctx* c, double out[3]) {
+  if (!c || !out) return LBM2P_EINVAL;
+  if (!c->inited) return LBM2P_ESTATE;
+  return c->prec ? bubble_f32(c, out) : bubble_f64(c, out);
+}
+
 int lbm2p_get_state(lbm2p_ctx* c, double* f, double* g, double* u) {
   if (!c) return LBM2P_EINVAL;
   if (!c->inited) return LBM2P_ESTATE;

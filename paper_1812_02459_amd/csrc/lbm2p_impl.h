@@ -205,6 +205,56 @@ __global__ __launch_bounds__(RED_NT) void k_reduce2(const double* part, int nb, 
   if (threadIdx.x < RED_K) out[threadIdx.x] = s[threadIdx.x][0];
 }
 
+// Bubble diagnostics of Sec. 4.5 (eq:quantify-yc, eq:quantify-uc): over the
+// nodes with phi < 0, their number, the sum of their row index y and the sum
+// of their vertical velocity, in float64 partials per workgroup (fixed tree
+// order), then one workgroup sums the partials.
+constexpr int BUB_K = 3;
+template <typename T>
+__global__ __launch_bounds__(RED_NT) void k_bubble1(const T* phi, const T* uy, int nx,
+                                                    long long n, double* part) {
+  __shared__ double s[BUB_K][RED_NT];
+  double c = 0, sy = 0, sv = 0;
+  for (long long id = (long long)blockIdx.x * RED_NT + threadIdx.x; id < n;
+       id += (long long)gridDim.x * RED_NT) {
+    if (double(phi[id]) < 0.0) {
+      c += 1.0;
+      sy += double(id / nx);
+      sv += double(uy[id]);
+    }
+  }
+  s[0][threadIdx.x] = c;
+  s[1][threadIdx.x] = sy;
+  s[2][threadIdx.x] = sv;
+  __syncthreads();
+  for (int w = RED_NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < BUB_K; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < BUB_K) part[(long long)blockIdx.x * BUB_K + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(RED_NT) void k_bubble2(const double* part, int nb, double* out) {
+  __shared__ double s[BUB_K][RED_NT];
+  double a[BUB_K] = {0, 0, 0};
+  for (int b = threadIdx.x; b < nb; b += RED_NT)
+    for (int k = 0; k < BUB_K; ++k) a[k] += part[b * BUB_K + k];
+  for (int k = 0; k < BUB_K; ++k) s[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = RED_NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < BUB_K; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double cnt = s[0][0];
+    out[0] = cnt;
+    out[1] = cnt > 0 ? s[1][0] / cnt : NAN;
+    out[2] = cnt > 0 ? s[2][0] / cnt : NAN;
+  }
+}
+
 constexpr int RED_BLOCKS = 1024;
 
 inline long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
@@ -587,6 +637,22 @@ int volume_impl(lbm2p_ctx* c, double out[6]) {
     return LBM2P_EHIP;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
   if (!std::isfinite(out[1]) || !std::isfinite(out[3])) return LBM2P_ENONFINITE;
+  return LBM2P_OK;
+}
+
+template <typename T>
+int bubble_impl(lbm2p_ctx* c, double out[3]) {
+  const int u = c->p.coupled ? c->uo : 0;
+  // the partials fit in the reduction scratch (RED_BLOCKS + 1) * RED_K doubles
+  static_assert(BUB_K <= RED_K, "bubble partials in the reduction scratch");
+  k_bubble1<T><<<RED_BLOCKS, RED_NT, 0, c->stream>>>((const T*)c->phi, (const T*)c->U[u][1],
+                                                     c->p.nx, c->n, c->red);
+  double* res = c->red + RED_BLOCKS * BUB_K;
+  k_bubble2<<<1, RED_NT, 0, c->stream>>>(c->red, RED_BLOCKS, res);
+  if (hipMemcpyAsync(out, res, BUB_K * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return LBM2P_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
   return LBM2P_OK;
 }
 

@@ -223,6 +223,39 @@ def rising_bubble(nx=256, ny=1024, R=32.0, xc=128.0, yc=128.0, sigma=None, Eo=10
                     dict(g=g, U_g=U_g, sigma0=sig0, R=R))
 
 
+# Sec. 4.5, Table IV: (Eo, Re, U_g, rho1/rho2, mu1/mu2)
+RISING_TESTS = {1: (10.0, 35.0, 0.0024, 10.0, 10.0), 2: (125.0, 35.0, 0.0019, 1000.0, 100.0)}
+
+
+def rising_bubble_benchmark(test=1, scale=1.0, steps=None, t_end=3.0):
+    """The rising-bubble benchmark of Sec. 4.5: a 1 x 2 domain on 240 x 480 nodes
+    (scale = 0.5: 120 x 240), periodic in x, no-slip walls in y, a gas bubble of
+    radius 0.25 at (0.5, 0.5), the Eo, Re, U_g and density and viscosity ratios of
+    Table IV, U_g = sqrt(2 g R) in lattice units.  rho1 = 1 (lattice), so
+    g = U_g^2/(2R), sigma = 2 rho1 U_g^2 R / Eo, mu1 = rho1 U_g 2R / Re; rho_ref =
+    rho1 (the liquid's head goes into the pressure).  Time unit: Table IV's own
+    units (rho1 = 1000, mu1 = 10, R = 0.25 in a domain of width 1, Re = 35) give
+    U_g = Re mu1 / (2 R rho1) = 0.7 per unit of length and time, so one time unit
+    is 0.7 L / U_g steps for a domain L nodes wide; `steps` defaults to t_end time
+    units."""
+    Eo, Re, U_g, rr, mr = RISING_TESTS[test]
+    nx, ny = int(round(240 * scale)), int(round(480 * scale))
+    R = 0.25 * nx
+    rho1 = 1.0
+    g = U_g * U_g / (2.0 * R)
+    sigma = 2.0 * rho1 * U_g * U_g * R / Eo
+    mu1 = rho1 * U_g * 2.0 * R / Re
+    phi = drop_field(nx, ny, 0.5 * nx, 0.5 * nx, R, 4.0, inside=-1.0, periodic=False)
+    z = np.zeros_like(phi)
+    prm = base_params(nx, ny, wall_x=False, wall_y=True, rho1=rho1, rho2=rho1 / rr,
+                      mu1=mu1, mu2=mu1 / mr, sigma=sigma, gy=-g, rho_ref=rho1)
+    steps_per_time = 0.7 * nx / U_g
+    if steps is None:
+        steps = int(round(t_end * steps_per_time))
+    return Workload(f"rising_test{test}", prm, phi, z, z.copy(), z.copy(), steps,
+                    dict(g=g, U_g=U_g, R=R, test=test, steps_per_time=steps_per_time))
+
+
 def random_smooth(nx, ny, seed, amp=1.0, modes=4):
     """A smooth random periodic field (sum of a few Fourier modes), for tests."""
     rng = np.random.default_rng(seed)

@@ -101,6 +101,8 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
         B.lbm2p_record(ctx, 4, 0, aligned, need)
     with pytest.raises(B.LBMError, match="call out of order"):
         B.lbm2p_adjoint(ctx, B.AdjointIO())                # nothing recorded
+    with pytest.raises(B.LBMError, match="call out of order"):
+        B.lbm2p_bubble(ctx)                                # before init
     B.lbm2p_destroy(ctx)
 
 

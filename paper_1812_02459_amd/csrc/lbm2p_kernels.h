@@ -12,6 +12,8 @@
 // the same nine locations of each distribution, so the update is in place.
 #pragma once
 
+#include <utility>
+
 #include "lbm2p_math.h"
 
 namespace lbm2p {
@@ -144,14 +146,17 @@ __device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, i
 // written once per kernel, so streaming accesses keep it from displacing the
 // fields the next passes read.  One bit per access kind and streaming parity:
 // bit PAR for the gather's loads, 2 + PAR for the collision's loads, 4 + PAR
-// for its stores.  Measured on 4096^2: nontemporal gather loads (both
-// parities) and nontemporal collision loads and stores in parity 1, where
-// every node reads and writes its own slots (aligned, whole cache lines), save
-// 4 % of the step; in parity 0 (shifted slots, partial lines at tile edges)
-// the hint slows the collision.  On lattices whose populations fit in the
-// cache the hints cost 2-3 % and are off.
+// for its stores; a set bit makes the access nontemporal where it is aligned
+// (`aligned`): in parity 1 every node reads and writes its own slots (whole
+// cache lines); in parity 0 the slots are shifted by c_i, and only the
+// directions with c_x = 0 (shifted by whole rows) stay aligned.  Measured on
+// 4096^2: nontemporal gather loads (both parities), nontemporal collision
+// loads and stores in parity 1 and the aligned parity-0 collision loads save
+// 5 % of the step; hinting the shifted parity-0 accesses slows the collision
+// by 5-9 %.  On lattices whose populations fit in the cache the hints cost
+// 2-3 % and are off.
 #ifndef LBM2P_POP_NT
-#define LBM2P_POP_NT 43
+#define LBM2P_POP_NT 47
 #endif
 template <int BIT, bool STREAM, typename T>
 __device__ __forceinline__ T pop_ld(const T* p) {
@@ -162,6 +167,19 @@ template <int BIT, bool STREAM, typename T>
 __device__ __forceinline__ void pop_st(T* p, T v) {
   if constexpr (STREAM && ((LBM2P_POP_NT >> BIT) & 1) != 0) __builtin_nontemporal_store(v, p);
   else *p = v;
+}
+// The collision's nine loads (v[i] from slot rd[i]) and stores (v[i] to slot
+// rd[opp(i)]) of one distribution, each with its direction's alignment known
+// at compile time.
+template <int PAR, bool STREAM, typename T, int... I>
+__device__ __forceinline__ void col_load9(const T* A, const int* rd, T* v,
+                                          std::integer_sequence<int, I...>) {
+  ((v[I] = pop_ld<2 + PAR, STREAM && (PAR == 1 || cx_of(I) == 0)>(A + rd[I])), ...);
+}
+template <int PAR, bool STREAM, typename T, int... I>
+__device__ __forceinline__ void col_store9(T* A, const int* rd, const T* v,
+                                           std::integer_sequence<int, I...>) {
+  (pop_st<4 + PAR, STREAM && (PAR == 1 || cx_of(I) == 0)>(A + rd[opp(I)], v[I]), ...);
 }
 
 // ------------------------------------------------------------- populations
@@ -747,11 +765,9 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
     T g[9];
     {
       T f[9], feq[9];
-#pragma unroll
-      for (int i = 0; i < 9; ++i) f[i] = pop_ld<2 + PAR, STREAM>(Af + rd[i]);
+      col_load9<PAR, STREAM>(Af, rd, f, std::make_integer_sequence<int, 9>{});
       if constexpr (COUPLED) {   // both distributions' loads in flight together
-#pragma unroll
-        for (int i = 0; i < 9; ++i) g[i] = pop_ld<2 + PAR, STREAM>(Ag + rd[i]);
+        col_load9<PAR, STREAM>(Ag, rd, g, std::make_integer_sequence<int, 9>{});
       }
       f_eq<T>(ph, tMu(lx, ly), u_x, u_y, P.eta, feq);
       if constexpr (std::is_same<T, float>::value) {
@@ -764,8 +780,7 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
         src_f<T>(ph, ax, ay, F);
         mrt_collide<T>(f, feq, F, P.s_f);
       }
-#pragma unroll
-      for (int i = 0; i < 9; ++i) pop_st<4 + PAR, STREAM>(Af + rd[opp(i)], f[i]);
+      col_store9<PAR, STREAM>(Af, rd, f, std::make_integer_sequence<int, 9>{});
     }
     if (COUPLED) {
       const T p = tPt(lx, ly);
@@ -795,8 +810,7 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
         src_g<T>(Frx, Fry, u_x, u_y, bx, by, G);
         mrt_collide<T>(g, geq, G, s);
       }
-#pragma unroll
-      for (int i = 0; i < 9; ++i) pop_st<4 + PAR, STREAM>(Ag + rd[opp(i)], g[i]);
+      col_store9<PAR, STREAM>(Ag, rd, g, std::make_integer_sequence<int, 9>{});
     }
   }
 }

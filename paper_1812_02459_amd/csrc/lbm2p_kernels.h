@@ -146,10 +146,11 @@ __device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, i
 // written once per kernel, so streaming accesses keep it from displacing the
 // fields the next passes read.  One bit per access kind and streaming parity:
 // bit PAR for the gather's loads, 2 + PAR for the collision's loads, 4 + PAR
-// for its stores; a set bit makes the access nontemporal where it is aligned
-// (`aligned`): in parity 1 every node reads and writes its own slots (whole
-// cache lines); in parity 0 the slots are shifted by c_i, and only the
-// directions with c_x = 0 (shifted by whole rows) stay aligned.  Measured on
+// for its stores.  A set bit makes the gather's loads nontemporal, and the
+// collision's accesses where they are aligned (col_load9, col_store9): in
+// parity 1 every node reads and writes its own slots (whole cache lines); in
+// parity 0 the slots are shifted by c_i, and only the directions with c_x = 0
+// (shifted by whole rows) stay aligned.  Measured on
 // 4096^2: nontemporal gather loads (both parities), nontemporal collision
 // loads and stores in parity 1 and the aligned parity-0 collision loads save
 // 5 % of the step; hinting the shifted parity-0 accesses slows the collision

@@ -128,3 +128,21 @@ def test_table4_rising_bubble(test):
     assert 0.1 * U_g <= vmax <= U_g
     if test == 1:
         assert fin2 and conv <= 0.05
+
+
+def test_table4_test1_fp32_follows_fp64():
+    """FP32 error statement on the benchmark (test 1 to t = 3): the FP32 run's y_c
+    stays within 0.01 domain widths of the FP64 run's and its V_c within 5 % of the
+    largest V_c, at every sample (bounds declared before the first run)."""
+    wl, _, t, _, y64, v64, f64 = _run(1, precision=0)
+    _, _, _, _, y32, v32, f32 = _run(1, precision=1)
+    nx = wl.params["nx"]
+    dy = float(np.max(np.abs(y32 - y64))) / nx
+    dv = float(np.max(np.abs(v32 - v64))) / float(np.max(v64))
+    print(f"test 1 FP32 vs FP64 to t = 3: max |dy_c| = {dy:.2e} widths, max |dV_c| = {dv:.2e} "
+          f"of max V_c", flush=True)
+    if OUT:
+        with open(os.path.join(OUT, "rising_bubble_test1_fp32.json"), "w") as fh:
+            json.dump(dict(dy_c_widths=dy, dV_c_rel=dv), fh, indent=1)
+    assert f64 and f32
+    assert dy <= 0.01 and dv <= 0.05

@@ -147,6 +147,15 @@ int lbm2p_volume(lbm2p_ctx* c, double out[6]);
  * Synchronises the stream.  ESTATE before init. */
 int lbm2p_bubble(lbm2p_ctx* c, double out[3]);
 
+/* Pressure jump of the Laplace test (Sec. 4.3): p' = rho p~ (the dynamic
+ * pressure from the kinematic p~ of the state, rho of clamp(phi) as eq:rho),
+ * averaged over the nodes with phi > 0.99 and over those with phi < -0.99.
+ * out[0] the jump <p'>_{phi>0.99} - <p'>_{phi<-0.99}, out[1] and out[2] the two
+ * means, out[3] and out[4] the two node counts, in host memory; a mean over no
+ * node is NaN.  Float64 sums in a fixed order.  Synchronises the stream.
+ * Coupled mode only (EINVAL in CH-only mode); ESTATE before init. */
+int lbm2p_pressure_jump(lbm2p_ctx* c, double out[5]);
+
 /* State in canonical order (post-collision f*_i(x), g*_i(x), then u~), as
  * device float64 arrays: d_f [9][ny][nx], d_g [9][ny][nx] (ignored in CH-only
  * mode, may be NULL), d_u [2][ny][nx].  set_state makes a context resume from

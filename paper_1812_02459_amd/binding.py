@@ -82,6 +82,7 @@ _sig = {
     "lbm2p_adjoint": [_vp, ctypes.POINTER(AdjointIO)],
     "lbm2p_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "lbm2p_bubble": [_vp, ctypes.POINTER(ctypes.c_double)],
+    "lbm2p_pressure_jump": [_vp, ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -173,6 +174,12 @@ def lbm2p_volume(ctx):
 def lbm2p_bubble(ctx):
     out = (ctypes.c_double * 3)()
     _check(_lib.lbm2p_bubble(ctx, out), "lbm2p_bubble")
+    return list(out)
+
+
+def lbm2p_pressure_jump(ctx):
+    out = (ctypes.c_double * 5)()
+    _check(_lib.lbm2p_pressure_jump(ctx, out), "lbm2p_pressure_jump")
     return list(out)
 
 
@@ -282,6 +289,12 @@ class Sim:
         eq:quantify-uc); y in row indices."""
         a, yc, vc = lbm2p_bubble(self.ctx)
         return dict(area=a, y_c=yc, V_c=vc)
+
+    def pressure_jump(self):
+        """<rho p~> over phi > 0.99 minus over phi < -0.99 (Sec. 4.3), the two means
+        and the two node counts."""
+        d, pin, pout, nin, nout = lbm2p_pressure_jump(self.ctx)
+        return dict(dp=d, p_in=pin, p_out=pout, n_in=nin, n_out=nout)
 
     def get_state(self):
         t = self.torch

@@ -404,6 +404,12 @@ int lbm2p_bubble(lbm2p_ctx* c, double out[3]) {
   return c->prec ? bubble_f32(c, out) : bubble_f64(c, out);
 }
 
+int lbm2p_pressure_jump(lbm2p_ctx* c, double out[5]) {
+  if (!c || !out || !c->p.coupled) return LBM2P_EINVAL;
+  if (!c->inited) return LBM2P_ESTATE;
+  return c->prec ? pjump_f32(c, out) : pjump_f64(c, out);
+}
+
 int lbm2p_get_state(lbm2p_ctx* c, double* f, double* g, double* u) {
   if (!c) return LBM2P_EINVAL;
   if (!c->inited) return LBM2P_ESTATE;

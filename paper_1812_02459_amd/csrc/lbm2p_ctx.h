@@ -110,6 +110,7 @@ namespace lbm2p {
   int moments_##SUF(lbm2p_ctx*, double*, double*, double*, double*, double*);    \
   int volume_##SUF(lbm2p_ctx*, double*);                                          \
   int bubble_##SUF(lbm2p_ctx*, double*);                                          \
+  int pjump_##SUF(lbm2p_ctx*, double*);                                           \
   int state_##SUF(lbm2p_ctx*, double*, double*, double*, int);                    \
   int to_f64_##SUF(lbm2p_ctx*, const void*, double*);                             \
   int record_##SUF(lbm2p_ctx*, int, int);                                         \

@@ -255,6 +255,56 @@ __global__ __launch_bounds__(RED_NT) void k_bubble2(const double* part, int nb, 
   }
 }
 
+// Pressure jump of the Laplace test (Sec. 4.3): over the nodes with phi > 0.99
+// and with phi < -0.99, the sums of p' = rho(clamp phi) p~ and the node counts,
+// in float64 partials per workgroup (fixed tree order).
+constexpr int PJ_K = 4;
+template <typename T>
+__global__ __launch_bounds__(RED_NT) void k_pjump1(const T* phi, const T* pt, long long n,
+                                                   double rho1, double rho2, double* part) {
+  __shared__ double s[PJ_K][RED_NT];
+  double a[PJ_K] = {0, 0, 0, 0};
+  for (long long id = (long long)blockIdx.x * RED_NT + threadIdx.x; id < n;
+       id += (long long)gridDim.x * RED_NT) {
+    const double ph = double(phi[id]);
+    const double c = ph < -1.0 ? -1.0 : (ph > 1.0 ? 1.0 : ph);
+    const double pp = (rho1 * (1.0 + c) / 2.0 + rho2 * (1.0 - c) / 2.0) * double(pt[id]);
+    if (ph > 0.99) {
+      a[0] += pp;
+      a[1] += 1.0;
+    } else if (ph < -0.99) {
+      a[2] += pp;
+      a[3] += 1.0;
+    }
+  }
+  for (int k = 0; k < PJ_K; ++k) s[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = RED_NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < PJ_K; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < PJ_K) part[(long long)blockIdx.x * PJ_K + threadIdx.x] = s[threadIdx.x][0];
+}
+
+// sums of K partials per workgroup over nb workgroups, one workgroup, fixed order
+template <int K>
+__global__ __launch_bounds__(RED_NT) void k_sum_parts(const double* part, int nb, double* out) {
+  __shared__ double s[K][RED_NT];
+  double a[K];
+  for (int k = 0; k < K; ++k) a[k] = 0;
+  for (int b = threadIdx.x; b < nb; b += RED_NT)
+    for (int k = 0; k < K; ++k) a[k] += part[b * K + k];
+  for (int k = 0; k < K; ++k) s[k][threadIdx.x] = a[k];
+  __syncthreads();
+  for (int w = RED_NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w)
+      for (int k = 0; k < K; ++k) s[k][threadIdx.x] += s[k][threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x < K) out[threadIdx.x] = s[threadIdx.x][0];
+}
+
 constexpr int RED_BLOCKS = 1024;
 
 inline long long align_up(long long v, long long a) { return (v + a - 1) / a * a; }
@@ -653,6 +703,27 @@ int bubble_impl(lbm2p_ctx* c, double out[3]) {
       hipSuccess)
     return LBM2P_EHIP;
   if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
+  return LBM2P_OK;
+}
+
+template <typename T>
+int pjump_impl(lbm2p_ctx* c, double out[5]) {
+  static_assert(PJ_K <= RED_K, "pressure-jump partials in the reduction scratch");
+  k_pjump1<T><<<RED_BLOCKS, RED_NT, 0, c->stream>>>((const T*)c->phi, (const T*)c->pt, c->n,
+                                                    c->p.rho1, c->p.rho2, c->red);
+  double* res = c->red + RED_BLOCKS * PJ_K;
+  k_sum_parts<PJ_K><<<1, RED_NT, 0, c->stream>>>(c->red, RED_BLOCKS, res);
+  double h[PJ_K];
+  if (hipMemcpyAsync(h, res, PJ_K * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return LBM2P_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
+  const double in = h[1] > 0 ? h[0] / h[1] : NAN, outm = h[3] > 0 ? h[2] / h[3] : NAN;
+  out[0] = in - outm;
+  out[1] = in;
+  out[2] = outm;
+  out[3] = h[1];
+  out[4] = h[3];
   return LBM2P_OK;
 }
 

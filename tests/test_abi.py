@@ -103,6 +103,16 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
         B.lbm2p_adjoint(ctx, B.AdjointIO())                # nothing recorded
     with pytest.raises(B.LBMError, match="call out of order"):
         B.lbm2p_bubble(ctx)                                # before init
+    with pytest.raises(B.LBMError, match="call out of order"):
+        B.lbm2p_pressure_jump(ctx)                         # before init
+    B.lbm2p_destroy(ctx)
+    ch = B.make_params(dict(ok, coupled=False), 0)
+    need = B.lbm2p_workspace_bytes(ch)
+    buf = ctypes.create_string_buffer(need + 512)
+    aligned = (ctypes.addressof(buf) + 255) // 256 * 256
+    ctx = B.lbm2p_create(ch, aligned, need, None)
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_pressure_jump(ctx)                         # no pressure in CH-only mode
     B.lbm2p_destroy(ctx)
 
 

@@ -235,6 +235,14 @@ def test_diagnostics_match_oracle():
     umag = (st.uo[0] ** 2 + st.uo[1] ** 2).sqrt()
     assert abs(v["max_u"] - float(umag.max())) <= 1e-15
     assert v["min_phi"] == float(st.phi.min()) and v["max_phi"] == float(st.phi.max())
+    # pressure jump (Sec. 4.3) against the oracle's on the oracle's own state (the
+    # GPU state equals it): counts exactly, the means to 1e-12 (sums in another order)
+    pj = sim.pressure_jump()
+    ref = D.pressure_jump(st.phi, st.p, wl.params["rho1"], wl.params["rho2"])
+    assert pj["n_in"] == int((st.phi > 0.99).sum()) > 0
+    assert pj["n_out"] == int((st.phi < -0.99).sum()) > 0
+    scale = max(abs(pj["p_in"]), abs(pj["p_out"]))
+    assert abs(pj["dp"] - ref) <= 1e-12 * scale, (pj, ref)
 
 
 def test_bitwise_determinism():

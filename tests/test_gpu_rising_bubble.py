@@ -41,7 +41,8 @@ OUT = os.environ.get("LBM2P_RESULTS_DIR")
 def test_bubble_diagnostics_match_oracle(precision):
     """lbm2p_bubble against the oracle's bubble_stats on the same fields (the GPU
     state's phi and u~ from lbm2p_moments): the area exactly, y_c and V_c to
-    1e-12 relative (float64 sums in another order).  Also the empty case."""
+    1e-12 relative (float64 sums in another order); lbm2p_pressure_jump against
+    the oracle's pressure_jump likewise.  Also the empty case."""
     from paper_1812_02459_amd.binding import Sim
     wl = I.rising_bubble_benchmark(1, scale=0.25)
     sim = Sim(wl.params, precision=precision)
@@ -55,6 +56,11 @@ def test_bubble_diagnostics_match_oracle(precision):
         assert b["area"] == area > 0
         assert abs(b["y_c"] - yc) <= 1e-12 * abs(yc)
         assert abs(b["V_c"] - vc) <= 1e-12 * abs(vc) + 1e-300
+        # the pressure-jump reduction on the same fields (Sec. 4.3)
+        pj = sim.pressure_jump()
+        ref = D.pressure_jump(m["phi"].cpu(), m["p"].cpu(), wl.params["rho1"], wl.params["rho2"])
+        assert pj["n_in"] == int((m["phi"] > 0.99).sum()) and pj["n_out"] == int((m["phi"] < -0.99).sum())
+        assert abs(pj["dp"] - ref) <= 1e-12 * max(abs(pj["p_in"]), abs(pj["p_out"]), 1e-300)
     sim.close()
     flat = Sim(wl.params, precision=precision)
     flat.init(np.ones_like(wl.phi0), wl.ux0, wl.uy0, wl.p0)

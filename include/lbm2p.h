@@ -147,6 +147,20 @@ int lbm2p_volume(lbm2p_ctx* c, double out[6]);
  * Synchronises the stream.  ESTATE before init. */
 int lbm2p_bubble(lbm2p_ctx* c, double out[3]);
 
+/* Residual of the velocity iteration, the paper's stopping measure (text
+ * after eq:Fmu): zeta = sum |u^K - u^{K-1}| / sum |u^{K-1}| over all nodes and
+ * both components, for the K fixed sweeps of a step (u^0 = u~ of the step
+ * before).  lbm2p_track_residual(c, 1) makes every later step run its last
+ * sweep as a launch of its own, so that u^{K-1} stays in a velocity plane
+ * (same results; one more launch per step for even K); 0 restores the
+ * two-sweep launches.  It does not apply inside lbm2p_record and
+ * lbm2p_adjoint.  EINVAL for on outside {0, 1}.
+ * lbm2p_residual: zeta of the last step, in float64 (0 when u^{K-1} = 0), in
+ * host memory; synchronises the stream.  ESTATE unless the last step ran with
+ * tracking on (and after init or set_state); EINVAL in CH-only mode. */
+int lbm2p_track_residual(lbm2p_ctx* c, int32_t on);
+int lbm2p_residual(lbm2p_ctx* c, double* out);
+
 /* Pressure jump of the Laplace test (Sec. 4.3): p' = rho p~ (the dynamic
  * pressure from the kinematic p~ of the state, rho of clamp(phi) as eq:rho),
  * averaged over the nodes with phi > 0.99 and over those with phi < -0.99.

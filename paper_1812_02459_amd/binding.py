@@ -83,6 +83,8 @@ _sig = {
     "lbm2p_stream_copy": [_vp, _vp, ctypes.c_size_t, _vp],
     "lbm2p_bubble": [_vp, ctypes.POINTER(ctypes.c_double)],
     "lbm2p_pressure_jump": [_vp, ctypes.POINTER(ctypes.c_double)],
+    "lbm2p_track_residual": [_vp, ctypes.c_int32],
+    "lbm2p_residual": [_vp, ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -175,6 +177,16 @@ def lbm2p_bubble(ctx):
     out = (ctypes.c_double * 3)()
     _check(_lib.lbm2p_bubble(ctx, out), "lbm2p_bubble")
     return list(out)
+
+
+def lbm2p_track_residual(ctx, on):
+    _check(_lib.lbm2p_track_residual(ctx, int(on)), "lbm2p_track_residual")
+
+
+def lbm2p_residual(ctx):
+    out = ctypes.c_double()
+    _check(_lib.lbm2p_residual(ctx, ctypes.byref(out)), "lbm2p_residual")
+    return out.value
 
 
 def lbm2p_pressure_jump(ctx):
@@ -289,6 +301,14 @@ class Sim:
         eq:quantify-uc); y in row indices."""
         a, yc, vc = lbm2p_bubble(self.ctx)
         return dict(area=a, y_c=yc, V_c=vc)
+
+    def track_residual(self, on=True):
+        """Keep the velocity iteration's residual of the following steps."""
+        lbm2p_track_residual(self.ctx, 1 if on else 0)
+
+    def residual(self):
+        """zeta = sum |u^K - u^{K-1}| / sum |u^{K-1}| of the last (tracked) step."""
+        return lbm2p_residual(self.ctx)
 
     def pressure_jump(self):
         """<rho p~> over phi > 0.99 minus over phi < -0.99 (Sec. 4.3), the two means

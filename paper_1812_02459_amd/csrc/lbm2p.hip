@@ -311,6 +311,8 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   c->from_init = 0;
   c->adj_ready = 0;
   c->adj_ws = nullptr;
+  c->track_resid = 0;
+  c->res_valid = 0;
   *out = c;
   return LBM2P_OK;
 }
@@ -354,7 +356,13 @@ int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, s
   if (bytes < L.total) return LBM2P_ENOSPACE;
   c->adj_ws = (char*)d_ws;
   c->adj_bytes = bytes;
-  return c->prec ? record_f32(c, nsteps, ckpt_every) : record_f64(c, nsteps, ckpt_every);
+  // the recorded steps and their recomputation run the same launches: no
+  // residual tracking inside record and adjoint
+  const int track = c->track_resid;
+  c->track_resid = 0;
+  const int r = c->prec ? record_f32(c, nsteps, ckpt_every) : record_f64(c, nsteps, ckpt_every);
+  c->track_resid = track;
+  return r;
 }
 
 int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
@@ -362,7 +370,11 @@ int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
   if (!c->inited || !c->adj_ready || c->steps != c->adj_steps_end) return LBM2P_ESTATE;
   if (io->dL_dphi0 && !io->phi0) return LBM2P_EINVAL;
   if (io->dL_dphi0 && !c->adj_from_init) return LBM2P_ESTATE;
-  return c->prec ? adjoint_f32(c, io) : adjoint_f64(c, io);
+  const int track = c->track_resid;
+  c->track_resid = 0;
+  const int r = c->prec ? adjoint_f32(c, io) : adjoint_f64(c, io);
+  c->track_resid = track;
+  return r;
 }
 
 int lbm2p_moments(lbm2p_ctx* c, double* phi, double* ux, double* uy, double* p, double* rho) {
@@ -402,6 +414,18 @@ int lbm2p_bubble(lbm2p_ctx* c, double out[3]) {
   if (!c || !out) return LBM2P_EINVAL;
   if (!c->inited) return LBM2P_ESTATE;
   return c->prec ? bubble_f32(c, out) : bubble_f64(c, out);
+}
+
+int lbm2p_track_residual(lbm2p_ctx* c, int32_t on) {
+  if (!c || (on != 0 && on != 1)) return LBM2P_EINVAL;
+  c->track_resid = on;
+  return LBM2P_OK;
+}
+
+int lbm2p_residual(lbm2p_ctx* c, double* out) {
+  if (!c || !out || !c->p.coupled) return LBM2P_EINVAL;
+  if (!c->inited || !c->res_valid) return LBM2P_ESTATE;
+  return c->prec ? resid_f32(c, out) : resid_f64(c, out);
 }
 
 int lbm2p_pressure_jump(lbm2p_ctx* c, double out[5]) {

@@ -22,6 +22,10 @@ struct lbm2p_ctx {
   double* red;     // reduction partials (+ 8 results)
   int uo;          // index of u~^n in U
   int uk_last;     // index of the last velocity iterate in uk
+  // velocity-iteration residual: with track_resid set, a step runs its last
+  // sweep alone and leaves its input u^{K-1} and output u^K in these planes
+  int track_resid, res_valid;
+  void *res_prev[2], *res_last[2];
   int parity;
   int inited;
   long long steps;
@@ -111,6 +115,7 @@ namespace lbm2p {
   int volume_##SUF(lbm2p_ctx*, double*);                                          \
   int bubble_##SUF(lbm2p_ctx*, double*);                                          \
   int pjump_##SUF(lbm2p_ctx*, double*);                                           \
+  int resid_##SUF(lbm2p_ctx*, double*);                                           \
   int state_##SUF(lbm2p_ctx*, double*, double*, double*, int);                    \
   int to_f64_##SUF(lbm2p_ctx*, const void*, double*);                             \
   int record_##SUF(lbm2p_ctx*, int, int);                                         \

@@ -16,6 +16,7 @@ int moments_f32(lbm2p_ctx* c, double* phi, double* ux, double* uy, double* p, do
 int volume_f32(lbm2p_ctx* c, double* out) { return volume_impl<float>(c, out); }
 int bubble_f32(lbm2p_ctx* c, double* out) { return bubble_impl<float>(c, out); }
 int pjump_f32(lbm2p_ctx* c, double* out) { return pjump_impl<float>(c, out); }
+int resid_f32(lbm2p_ctx* c, double* out) { return resid_impl<float>(c, out); }
 int state_f32(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
   return state_impl<float>(c, f, g, u, set);
 }

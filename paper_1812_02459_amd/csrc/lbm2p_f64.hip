@@ -15,6 +15,7 @@ int moments_f64(lbm2p_ctx* c, double* phi, double* ux, double* uy, double* p, do
 int volume_f64(lbm2p_ctx* c, double* out) { return volume_impl<double>(c, out); }
 int bubble_f64(lbm2p_ctx* c, double* out) { return bubble_impl<double>(c, out); }
 int pjump_f64(lbm2p_ctx* c, double* out) { return pjump_impl<double>(c, out); }
+int resid_f64(lbm2p_ctx* c, double* out) { return resid_impl<double>(c, out); }
 int state_f64(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
   return state_impl<double>(c, f, g, u, set);
 }

@@ -287,6 +287,32 @@ __global__ __launch_bounds__(RED_NT) void k_pjump1(const T* phi, const T* pt, lo
   if (threadIdx.x < PJ_K) part[(long long)blockIdx.x * PJ_K + threadIdx.x] = s[threadIdx.x][0];
 }
 
+// Velocity-iteration residual (the paper's stopping measure after eq:Fmu):
+// sum over nodes of |u^K - u^{K-1}| (both components) and of |u^{K-1}|.
+template <typename T>
+__global__ __launch_bounds__(RED_NT) void k_resid1(const T* ax, const T* ay, const T* bx,
+                                                   const T* by, long long n, double* part) {
+  __shared__ double s[2][RED_NT];
+  double num = 0, den = 0;
+  for (long long id = (long long)blockIdx.x * RED_NT + threadIdx.x; id < n;
+       id += (long long)gridDim.x * RED_NT) {
+    const double px = double(bx[id]), py = double(by[id]);
+    num += fabs(double(ax[id]) - px) + fabs(double(ay[id]) - py);
+    den += fabs(px) + fabs(py);
+  }
+  s[0][threadIdx.x] = num;
+  s[1][threadIdx.x] = den;
+  __syncthreads();
+  for (int w = RED_NT / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      s[0][threadIdx.x] += s[0][threadIdx.x + w];
+      s[1][threadIdx.x] += s[1][threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 2) part[(long long)blockIdx.x * 2 + threadIdx.x] = s[threadIdx.x][0];
+}
+
 // sums of K partials per workgroup over nb workgroups, one workgroup, fixed order
 template <int K>
 __global__ __launch_bounds__(RED_NT) void k_sum_parts(const double* part, int nb, double* out) {
@@ -549,11 +575,14 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       using C = StepCfg<T>;
       const Tiles<C::TX, C::VEL_TY> tv(p);
       int done = 0, launch = 0;
+      // residual tracking (outside record mode): the last sweep runs alone, so
+      // that its input u^{K-1} stays in a plane (u~^n for K = 1)
+      const bool track = c->track_resid && !c->rec;
       while (done < p.K) {
         // two sweeps per launch, one for an odd remainder; when recording for
         // the adjoint, every iterate u^{s+1} goes to its own plane rec_uk[s]
         // (the two-sweep kernel then also writes its first sweep's result)
-        const bool two = p.K - done >= 2;
+        const bool two = p.K - done >= (track ? 3 : 2);
         const int last = done + (two ? 1 : 0);
         T* ox = (T*)(c->rec ? c->rec_uk[last][0] : c->uk[launch & 1][0]);
         T* oy = (T*)(c->rec ? c->rec_uk[last][1] : c->uk[launch & 1][1]);
@@ -567,11 +596,18 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
           k_vel<T, 1, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
               K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
         done += two ? 2 : 1;
+        if (done == p.K) {
+          c->res_prev[0] = (void*)ux;
+          c->res_prev[1] = (void*)uy;
+          c->res_last[0] = ox;
+          c->res_last[1] = oy;
+        }
         ux = ox;
         uy = oy;
         ++launch;
       }
       c->uk_last = (launch - 1) & 1;
+      c->res_valid = track ? 1 : 0;
       if (p.compact) {
         ProfScope ps(c, PASS_FILTER);
         const T* pr = (const T*)c->praw;
@@ -646,6 +682,7 @@ int init_impl(lbm2p_ctx* c, const double* phi0, const double* ux0, const double*
   c->inited = 1;
   c->from_init = 1;
   c->adj_ready = 0;
+  c->res_valid = 0;
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
 
@@ -728,11 +765,27 @@ int pjump_impl(lbm2p_ctx* c, double out[5]) {
 }
 
 template <typename T>
+int resid_impl(lbm2p_ctx* c, double* out) {
+  k_resid1<T><<<RED_BLOCKS, RED_NT, 0, c->stream>>>(
+      (const T*)c->res_last[0], (const T*)c->res_last[1], (const T*)c->res_prev[0],
+      (const T*)c->res_prev[1], c->n, c->red);
+  double* res = c->red + RED_BLOCKS * 2;
+  k_sum_parts<2><<<1, RED_NT, 0, c->stream>>>(c->red, RED_BLOCKS, res);
+  double h[2];
+  if (hipMemcpyAsync(h, res, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream) != hipSuccess)
+    return LBM2P_EHIP;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
+  *out = h[1] > 0 ? h[0] / h[1] : 0.0;
+  return LBM2P_OK;
+}
+
+template <typename T>
 int state_impl(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
   const KParams<T> K = kparams<T>(c);
   if (set) {
     c->from_init = 0;
     c->adj_ready = 0;
+    c->res_valid = 0;
   }
   if (f) k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Af, f, c->parity, set, 0.0);
   if (g && c->p.coupled)

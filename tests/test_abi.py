@@ -105,6 +105,11 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
         B.lbm2p_bubble(ctx)                                # before init
     with pytest.raises(B.LBMError, match="call out of order"):
         B.lbm2p_pressure_jump(ctx)                         # before init
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_track_residual(ctx, 2)
+    B.lbm2p_track_residual(ctx, 1)                         # host-side switch
+    with pytest.raises(B.LBMError, match="call out of order"):
+        B.lbm2p_residual(ctx)                              # no tracked step yet
     B.lbm2p_destroy(ctx)
     ch = B.make_params(dict(ok, coupled=False), 0)
     need = B.lbm2p_workspace_bytes(ch)
@@ -113,6 +118,8 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
     ctx = B.lbm2p_create(ch, aligned, need, None)
     with pytest.raises(B.LBMError, match="invalid argument"):
         B.lbm2p_pressure_jump(ctx)                         # no pressure in CH-only mode
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_residual(ctx)                              # no velocity iteration either
     B.lbm2p_destroy(ctx)
 
 

@@ -245,6 +245,36 @@ def test_diagnostics_match_oracle():
     assert abs(pj["dp"] - ref) <= 1e-12 * scale, (pj, ref)
 
 
+@pytest.mark.parametrize("kw", [dict(K=1), dict(K=2), dict(K=3, wall_y=True),
+                                dict(K=4, wall_x=True, wall_y=True)])
+def test_velocity_residual_matches_oracle(kw):
+    """The velocity iteration's residual zeta of the last step (lbm2p_residual,
+    with tracking on) against the oracle's, to 1e-12 (float64 sums in another
+    order); tracking runs the last sweep alone, and the state stays bitwise the
+    untracked run's.  Without tracking, or before a tracked step, ESTATE."""
+    from paper_1812_02459_amd.binding import LBMError
+    wl = droplet_case(48, 40, seed=11, **kw)
+    st, prm = oracle_init(wl)
+    sim = gpu_sim(wl)
+    plain = gpu_sim(wl)
+    sim.track_residual(True)
+    with pytest.raises(LBMError, match="call out of order"):
+        sim.residual()
+    for n in (1, 4):
+        st = oracle.run(st, prm, n)
+        sim.step(n)
+        plain.step(n)
+        z = sim.residual()
+        print(kw, n, z, st.resid, flush=True)
+        assert st.resid > 0 and abs(z - st.resid) <= 1e-12 * st.resid
+        for a, b in zip(sim.get_state(), plain.get_state()):
+            assert torch.equal(a, b)
+    sim.track_residual(False)
+    sim.step(1)
+    with pytest.raises(LBMError, match="call out of order"):
+        sim.residual()
+
+
 def test_bitwise_determinism():
     wl = droplet_case(64, 64, seed=7)
     outs = []

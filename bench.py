@@ -290,6 +290,9 @@ def main():
         if not args.no_fp64:
             res["fp64"] = adjoint_cost(0, args.adj_steps)
         res["fp32_compact_filter"] = adjoint_cost(1, args.adj_steps, compact=True)
+        res["fp32_all_steps_kept"] = adjoint_cost(1, args.adj_steps, k=args.adj_steps)
+        if not args.no_fp64:
+            res["fp64_all_steps_kept"] = adjoint_cost(0, args.adj_steps, k=args.adj_steps)
         print(json.dumps({"adjoint": res}), flush=True)
         return
     t0 = time.perf_counter()
@@ -316,9 +319,18 @@ def main():
         if not args.no_fp64:
             adj["fp64"] = adjoint_cost(0, args.adj_steps)
         adj["fp32_compact_filter"] = adjoint_cost(1, args.adj_steps, compact=True)
+        # every step's intermediates kept (checkpoint interval = run length: one
+        # segment, kept by the record, so the adjoint recomputes nothing);
+        # workspace 8.2 GB FP32, 16.4 GB FP64 for 640 steps at 256 x 1024
+        adj["fp32_all_steps_kept"] = adjoint_cost(1, args.adj_steps, k=args.adj_steps)
+        if not args.no_fp64:
+            adj["fp64_all_steps_kept"] = adjoint_cost(0, args.adj_steps, k=args.adj_steps)
         print(f"# adjoint/forward: fp32 {adj['fp32']['ratio']:.2f}"
               + (f", fp64 {adj['fp64']['ratio']:.2f}" if "fp64" in adj else "")
-              + f", fp32 compact filter {adj['fp32_compact_filter']['ratio']:.2f}",
+              + f", fp32 compact filter {adj['fp32_compact_filter']['ratio']:.2f}"
+              + f"; all steps kept: fp32 {adj['fp32_all_steps_kept']['ratio']:.2f}"
+              + (f", fp64 {adj['fp64_all_steps_kept']['ratio']:.2f}"
+                 if "fp64_all_steps_kept" in adj else ""),
               file=sys.stderr, flush=True)
     variants = None
     if not args.no_variants:

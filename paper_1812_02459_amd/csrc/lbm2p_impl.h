@@ -560,10 +560,14 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       k_copy<T><<<blocks1d(n), 256, 0, st>>>(phibar, phi, n);
     } else {
       using C = StepCfg<T>;
-      if (Tiles<C::TX, C::FD_TY>(p).tx * (long long)Tiles<C::TX, C::FD_TY>(p).ty >= FD_MIN_TILES)
+      const Tiles<C::TX, C::FD_TY> tl(p);
+      const Tiles<C::TX, C::FDS_TY> tls(p);
+      if (tl.tx * (long long)tl.ty >= FD_MIN_TILES)
         launch_fd<T, C::FD_TY, C::FD_NT>(c, K, st, phibar, phi1, phi2, phi);
-      else
+      else if (tls.tx * (long long)tls.ty >= FD_TINY_TILES)
         launch_fd<T, C::FDS_TY, C::FDS_NT>(c, K, st, phibar, phi1, phi2, phi);
+      else
+        launch_fd<T, C::FDT_TY, C::FDT_NT>(c, K, st, phibar, phi1, phi2, phi);
     }
     if (p.coupled) {
       T* uox = (T*)c->U[c->uo][0];

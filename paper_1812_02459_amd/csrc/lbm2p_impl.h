@@ -496,6 +496,18 @@ void launch_collide(lbm2p_ctx* c, const KParams<T>& K, int par, hipStream_t st, 
                     const T* uoy) {
   using C = StepCfg<T>;
   const Tiles<C::COL_TX, C::COL_TY> tc(c->p);
+  if constexpr (!STREAM) {   // small lattices (never streamed): the small tiles
+    if (tc.tx * (long long)tc.ty < TINY_TILES) {
+      const Tiles<C::COLT_TX, C::COLT_TY> tt(c->p);
+      if (par == 0)
+        k_collide<T, 0, COUPLED, STREAM, C::COLT_TX, C::COLT_TY, C::COLT_NT>
+            <<<tt.grid(), C::COLT_NT, 0, st>>>(K, tt.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
+      else
+        k_collide<T, 1, COUPLED, STREAM, C::COLT_TX, C::COLT_TY, C::COLT_NT>
+            <<<tt.grid(), C::COLT_NT, 0, st>>>(K, tt.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
+      return;
+    }
+  }
   if (par == 0)
     k_collide<T, 0, COUPLED, STREAM, C::COL_TX, C::COL_TY, C::COL_NT>
         <<<tc.grid(), C::COL_NT, 0, st>>>(K, tc.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
@@ -564,7 +576,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       const Tiles<C::TX, C::FDS_TY> tls(p);
       if (tl.tx * (long long)tl.ty >= FD_MIN_TILES)
         launch_fd<T, C::FD_TY, C::FD_NT>(c, K, st, phibar, phi1, phi2, phi);
-      else if (tls.tx * (long long)tls.ty >= FD_TINY_TILES)
+      else if (tls.tx * (long long)tls.ty >= TINY_TILES)
         launch_fd<T, C::FDS_TY, C::FDS_NT>(c, K, st, phibar, phi1, phi2, phi);
       else
         launch_fd<T, C::FDT_TY, C::FDT_NT>(c, K, st, phibar, phi1, phi2, phi);

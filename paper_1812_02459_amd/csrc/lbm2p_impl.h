@@ -536,6 +536,34 @@ void launch_fd(lbm2p_ctx* c, const KParams<T>& K, hipStream_t st, T* phibar, T* 
   }
 }
 
+// one velocity launch (two sweeps, or one) with TY x NT tiles
+template <typename T, int TY, int NT>
+void launch_vel(const lbm2p_params& p, const KParams<T>& K, hipStream_t st, bool two, const T* phi,
+                const T* praw, const T* jx, const T* jy, const T* ux, const T* uy, T* ox, T* oy,
+                T* o1x, T* o1y) {
+  constexpr int TX = StepCfg<T>::TX;
+  const Tiles<TX, TY> tv(p);
+  if (two)
+    k_vel2<T, TX, TY, NT><<<tv.grid(), NT, 0, st>>>(K, tv.tx, phi, praw, jx, jy, ux, uy, ox, oy,
+                                                    o1x, o1y);
+  else
+    k_vel<T, 1, TX, TY, NT><<<tv.grid(), NT, 0, st>>>(K, tv.tx, phi, praw, jx, jy, ux, uy, ox, oy);
+}
+
+// the explicit filter SF-(2N+1) with TY x NT tiles
+template <typename T, int TY, int NT>
+void launch_filter(const lbm2p_ctx* c, const KParams<T>& K, hipStream_t st, const T* pr,
+                   const T* ux, const T* uy, T* po, T* unx, T* uny) {
+  constexpr int TX = StepCfg<T>::TX;
+  const Tiles<TX, TY> tf(c->p);
+  switch (c->fn) {
+    case 2: k_filter<T, 2, TX, TY, NT><<<tf.grid(), NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+    case 3: k_filter<T, 3, TX, TY, NT><<<tf.grid(), NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+    case 4: k_filter<T, 4, TX, TY, NT><<<tf.grid(), NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+    default: k_filter<T, 5, TX, TY, NT><<<tf.grid(), NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
+  }
+}
+
 template <typename T>
 int step_impl(lbm2p_ctx* c, int nsteps) {
   const lbm2p_params& p = c->p;
@@ -579,7 +607,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       else if (tls.tx * (long long)tls.ty >= TINY_TILES)
         launch_fd<T, C::FDS_TY, C::FDS_NT>(c, K, st, phibar, phi1, phi2, phi);
       else
-        launch_fd<T, C::FDT_TY, C::FDT_NT>(c, K, st, phibar, phi1, phi2, phi);
+        launch_fd<T, TINY_TY, TINY_NT>(c, K, st, phibar, phi1, phi2, phi);
     }
     if (p.coupled) {
       T* uox = (T*)c->U[c->uo][0];
@@ -605,12 +633,12 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         T* o1x = (T*)(c->rec && two ? c->rec_uk[done][0] : nullptr);
         T* o1y = (T*)(c->rec && two ? c->rec_uk[done][1] : nullptr);
         ProfScope ps(c, PASS_VEL);
-        if (two)
-          k_vel2<T, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
-              K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
+        if (tv.tx * (long long)tv.ty < TINY_TILES)
+          launch_vel<T, TINY_TY, TINY_NT>(
+              p, K, st, two, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
         else
-          k_vel<T, 1, C::TX, C::VEL_TY, C::VEL_NT><<<tv.grid(), C::VEL_NT, 0, st>>>(
-              K, tv.tx, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy);
+          launch_vel<T, C::VEL_TY, C::VEL_NT>(p, K, st, two, phi, (T*)c->praw, (T*)c->jx,
+                                              (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
         done += two ? 2 : 1;
         if (done == p.K) {
           c->res_prev[0] = (void*)ux;
@@ -643,12 +671,10 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         const Tiles<C::TX, C::FIL_TY> tf(p);
         const T* pr = (const T*)c->praw;
         T* po = (T*)c->pt;
-        switch (c->fn) {
-          case 2: k_filter<T, 2, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-          case 3: k_filter<T, 3, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-          case 4: k_filter<T, 4, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-          default: k_filter<T, 5, C::TX, C::FIL_TY, C::FIL_NT><<<tf.grid(), C::FIL_NT, 0, st>>>(K, tf.tx, pr, ux, uy, po, unx, uny); break;
-        }
+        if (tf.tx * (long long)tf.ty < TINY_TILES)
+          launch_filter<T, TINY_TY, TINY_NT>(c, K, st, pr, ux, uy, po, unx, uny);
+        else
+          launch_filter<T, C::FIL_TY, C::FIL_NT>(c, K, st, pr, ux, uy, po, unx, uny);
       }
       {
         ProfScope ps(c, PASS_COLLIDE);

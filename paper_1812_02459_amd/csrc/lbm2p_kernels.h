@@ -25,26 +25,26 @@ namespace lbm2p {
 // tiles recompute fewer halo nodes but hold more LDS per workgroup.
 // Compile-time tuning parameters, measured on 4096^2.
 // The FD stage has a second, smaller shape (FDS) for lattices on which the
-// first would give fewer than FD_MIN_TILES workgroups, and a third (FDT, 8 rows)
-// for lattices on which FDS would give fewer than TINY_TILES; the collision has
-// a small shape (COLT) for lattices on which its own gives fewer than
-// TINY_TILES.  There each pass is one workgroup's latency, which shorter tiles
-// cut (128^2 CH-only step 29 -> 20 us FP32; 200^2 droplet 73 -> 51 us FP64).
+// first would give fewer than FD_MIN_TILES workgroups.  On lattices where a
+// pass's own shape gives fewer than TINY_TILES workgroups, each pass is one
+// workgroup's latency, which shorter tiles cut: the FD stages, the velocity
+// sweeps and the filter then take 64 x TINY_TY tiles of TINY_NT threads, the
+// collision its COLT shape (128^2 CH-only step 29 -> 20 us FP32; 200^2
+// droplet 53 -> 34 us FP32, 77 -> 49 us FP64).
 #ifndef LBM2P_F32_TILES
-#define LBM2P_F32_TILES 64, 1024, 16, 512, 32, 512, 16, 512, 128, 32, 512, 8, 512, 8, 512, 64
+#define LBM2P_F32_TILES 64, 1024, 16, 512, 32, 512, 16, 512, 128, 32, 512, 8, 512, 64
 #endif
 #ifndef LBM2P_F64_TILES
-#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256, 64, 16, 512, 8, 512, 4, 256, 64
+#define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256, 64, 16, 512, 4, 256, 64
 #endif
-constexpr int FD_MIN_TILES = 512, TINY_TILES = 64;
+constexpr int FD_MIN_TILES = 512, TINY_TILES = 64, TINY_TY = 8, TINY_NT = 512;
 template <int FD_Y, int FD_T, int VEL_Y, int VEL_T, int FIL_Y, int FIL_T, int COL_Y, int COL_T,
-          int COL_X, int FDS_Y, int FDS_T, int FDT_Y, int FDT_T, int COLT_Y, int COLT_T,
-          int COLT_X>
+          int COL_X, int FDS_Y, int FDS_T, int COLT_Y, int COLT_T, int COLT_X>
 struct StepTiles {
   static constexpr int TX = 64, COL_TX = COL_X;
   static constexpr int FD_TY = FD_Y, FD_NT = FD_T, VEL_TY = VEL_Y, VEL_NT = VEL_T;
   static constexpr int FIL_TY = FIL_Y, FIL_NT = FIL_T, COL_TY = COL_Y, COL_NT = COL_T;
-  static constexpr int FDS_TY = FDS_Y, FDS_NT = FDS_T, FDT_TY = FDT_Y, FDT_NT = FDT_T;
+  static constexpr int FDS_TY = FDS_Y, FDS_NT = FDS_T;
   static constexpr int COLT_TY = COLT_Y, COLT_NT = COLT_T, COLT_TX = COLT_X;
 };
 template <typename T>

@@ -113,10 +113,22 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes,
 /* Initial state (equilibrium populations, eq:feq_CH / eq:geq with
  * mu = mu_phi(phi0), eq:chemical): f* = f^eq(phi0, mu, u0), g* = g^eq(p0, u0),
  * u~ = u0.  Device float64 planes [ny][nx]; d_ux0/d_uy0/d_p0 may be NULL
- * (zeros).  In CH-only mode (u0x, u0y) is the prescribed velocity for every
- * later step. */
+ * (zeros).  In CH-only mode (u0x, u0y) is the prescribed velocity of the
+ * later steps (until lbm2p_set_velocity). */
 int lbm2p_init_fields(lbm2p_ctx* c, const double* d_phi0, const double* d_ux0,
                       const double* d_uy0, const double* d_p0);
+
+/* CH-only mode: the prescribed velocity of every later step, until the next
+ * call (Sec. 4.1: the single vortex, whose velocity field is modulated in time
+ * by cos(pi t / T); Sec. 4.2: the translating drop).  d_ux, d_uy: device
+ * float64 planes [ny][nx], borrowed for the call (converted to the context's
+ * precision).  The first step after the call takes d_t u of eq:Fi as the new
+ * velocity minus the one the previous step used (the backward difference the
+ * coupled mode takes of u~); a velocity held fixed has d_t u = 0.  EINVAL in
+ * coupled mode (the velocity there is the solution of Eq:u) or for a NULL
+ * pointer; ESTATE before init.  lbm2p_record returns ESTATE between this call
+ * and the next step, and a record made before it can no longer be reversed. */
+int lbm2p_set_velocity(lbm2p_ctx* c, const double* d_ux, const double* d_uy);
 
 /* Advance n >= 0 time steps (asynchronous). ESTATE before init. */
 int lbm2p_step(lbm2p_ctx* c, int32_t n);
@@ -209,7 +221,8 @@ int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t
  * the per-step intermediates of its last segment, in d_ws (device memory,
  * 256-byte aligned, >= the bytes above, owned by the caller and kept alive
  * until the last lbm2p_adjoint of this record returns or the next record).
- * ESTATE before init; EINVAL for invalid values; ENOSPACE for a small d_ws. */
+ * ESTATE before init or right after lbm2p_set_velocity (see there); EINVAL for
+ * invalid values; ENOSPACE for a small d_ws. */
 int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes);
 
 /* Inputs (seeds) and outputs of lbm2p_adjoint.  Device float64 arrays in the

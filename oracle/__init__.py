@@ -33,4 +33,4 @@ Readings of places where the paper is silent or garbled are listed in
 """
 
 from . import lattice, ops, step, diagnostics, analytic  # noqa: F401
-from .step import Params, State, init_state, step as step_once, run  # noqa: F401
+from .step import Params, State, init_state, set_velocity, step as step_once, run  # noqa: F401

@@ -65,7 +65,9 @@ R16 gravity enters as F_g = (rho - rho_ref) g; rho_ref = mean density on a fully
     periodic box (constant, since sum phi is conserved), 0 with walls.
 R17 eta = M / (c_s^2 (tau_f - 1/2)) from eq:mobility, eta being "adjustable for a
     given mobility".
-R18 CH-only mode (prescribed velocity, no hydrodynamics): d_t u = 0, u~ = u.
+R18 CH-only mode (prescribed velocity, no hydrodynamics): u~ = the prescribed u;
+    d_t u in eq:Fi is the backward difference of the prescribed velocities of
+    consecutive steps (R12's difference), 0 for a velocity held fixed.
 R19 "original CH" (Sec. 4.1-4.3 comparisons, lambda = 0) means no FD sub-step at all.
 """
 
@@ -139,6 +141,8 @@ class State:
     j: Optional[torch.Tensor] = None
     uK: Optional[torch.Tensor] = None
     resid: Optional[float] = None
+    # CH-only: the velocity the last step used, when set_velocity has replaced it
+    up: Optional[torch.Tensor] = None
 
 
 # ----------------------------------------------------------------------------
@@ -501,7 +505,8 @@ def step(st, prm):
     phi = phibar if prm.original_ch else rk3(phibar, lambda q: fd_rhs(q, prm))
     uox, uoy = st.uo[0], st.uo[1]
     if not prm.coupled:
-        fst, _ = collide(f, None, phi, None, uox, uoy, uox, uoy, prm)
+        prev = st.uo if st.up is None else st.up
+        fst, _ = collide(f, None, phi, None, uox, uoy, prev[0], prev[1], prm)
         return State(fs=torch.stack(fst), gs=None, uo=st.uo, n=st.n + 1,
                      phi=phi, phibar=phibar)
     uKx, uKy, resid = velocity_iteration(phi, praw, jx, jy, uox, uoy, prm)
@@ -510,6 +515,14 @@ def step(st, prm):
     return State(fs=torch.stack(fst), gs=torch.stack(gst), uo=torch.stack([utx, uty]),
                  n=st.n + 1, phi=phi, p=pt, phibar=phibar, praw=praw,
                  j=torch.stack([jx, jy]), uK=torch.stack([uKx, uKy]), resid=resid)
+
+
+def set_velocity(st, ux, uy):
+    """CH-only mode: prescribe the velocity of the following steps (Sec. 4.1's
+    vortex is modulated in time, cos(pi t / T)).  The next step's d_t u is the
+    new velocity minus the one the last step used (R18)."""
+    prev = st.uo if st.up is None else st.up
+    return dataclasses.replace(st, uo=torch.stack([ux.to(DT), uy.to(DT)]), up=prev)
 
 
 def run(st, prm, nsteps):

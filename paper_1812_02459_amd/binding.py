@@ -85,6 +85,7 @@ _sig = {
     "lbm2p_pressure_jump": [_vp, ctypes.POINTER(ctypes.c_double)],
     "lbm2p_track_residual": [_vp, ctypes.c_int32],
     "lbm2p_residual": [_vp, ctypes.POINTER(ctypes.c_double)],
+    "lbm2p_set_velocity": [_vp, _vp, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -150,6 +151,10 @@ def lbm2p_create(p, ws_ptr, nbytes, stream_ptr):
 def lbm2p_init_fields(ctx, phi0, ux0, uy0, p0):
     _check(_lib.lbm2p_init_fields(ctx, _vp(phi0), _vp(ux0), _vp(uy0), _vp(p0)),
            "lbm2p_init_fields")
+
+
+def lbm2p_set_velocity(ctx, ux, uy):
+    _check(_lib.lbm2p_set_velocity(ctx, _vp(ux), _vp(uy)), "lbm2p_set_velocity")
 
 
 def lbm2p_step(ctx, n):
@@ -275,6 +280,13 @@ class Sim:
 
     def step(self, n=1):
         lbm2p_step(self.ctx, n)
+        return self
+
+    def set_velocity(self, ux, uy):
+        """CH-only mode: the prescribed velocity of the following steps."""
+        ux, uy = self._dev(ux), self._dev(uy)
+        lbm2p_set_velocity(self.ctx, ux.data_ptr(), uy.data_ptr())
+        self._vel = (ux, uy)          # alive until the stream has consumed them
         return self
 
     def _plane(self):

@@ -313,6 +313,7 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   c->adj_ws = nullptr;
   c->track_resid = 0;
   c->res_valid = 0;
+  c->vpend = 0;
   *out = c;
   return LBM2P_OK;
 }
@@ -338,6 +339,12 @@ int lbm2p_step(lbm2p_ctx* c, int32_t n) {
   return c->prec ? step_f32(c, n) : step_f64(c, n);
 }
 
+int lbm2p_set_velocity(lbm2p_ctx* c, const double* ux, const double* uy) {
+  if (!c || !ux || !uy || c->p.coupled) return LBM2P_EINVAL;
+  if (!c->inited) return LBM2P_ESTATE;
+  return c->prec ? setvel_f32(c, ux, uy) : setvel_f64(c, ux, uy);
+}
+
 int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t ckpt_every,
                                   size_t* bytes) {
   const int e = validate(p);
@@ -351,7 +358,9 @@ int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t
 
 int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes) {
   if (!c || nsteps < 0 || ckpt_every < 1 || !d_ws || ((uintptr_t)d_ws & 255)) return LBM2P_EINVAL;
-  if (!c->inited) return LBM2P_ESTATE;
+  // a velocity set since the last step: that step's d_t u is not a constant of
+  // the recorded run, which the reverse of the CH-only collision assumes
+  if (!c->inited || c->vpend) return LBM2P_ESTATE;
   const AdjLayout L = adj_layout(c->p, c->ps, c->n, c->esz, nsteps, ckpt_every);
   if (bytes < L.total) return LBM2P_ENOSPACE;
   c->adj_ws = (char*)d_ws;

@@ -21,6 +21,9 @@ struct lbm2p_ctx {
   void* U[2][2];   // filtered velocity, double buffered (u~^n and u~^{n+1})
   double* red;     // reduction partials (+ 8 results)
   int uo;          // index of u~^n in U
+  // CH-only mode: the prescribed velocity is U[0]; after lbm2p_set_velocity
+  // (vpend = 1) U[1] holds the velocity the last step used, for d_t u
+  int vpend;
   int uk_last;     // index of the last velocity iterate in uk
   // velocity-iteration residual: with track_resid set, a step runs its last
   // sweep alone and leaves its input u^{K-1} and output u^K in these planes
@@ -117,6 +120,7 @@ namespace lbm2p {
   int pjump_##SUF(lbm2p_ctx*, double*);                                           \
   int resid_##SUF(lbm2p_ctx*, double*);                                           \
   int state_##SUF(lbm2p_ctx*, double*, double*, double*, int);                    \
+  int setvel_##SUF(lbm2p_ctx*, const double*, const double*);                     \
   int to_f64_##SUF(lbm2p_ctx*, const void*, double*);                             \
   int record_##SUF(lbm2p_ctx*, int, int);                                         \
   int adjoint_##SUF(lbm2p_ctx*, lbm2p_adjoint_io*);

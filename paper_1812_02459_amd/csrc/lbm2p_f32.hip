@@ -20,6 +20,9 @@ int resid_f32(lbm2p_ctx* c, double* out) { return resid_impl<float>(c, out); }
 int state_f32(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
   return state_impl<float>(c, f, g, u, set);
 }
+int setvel_f32(lbm2p_ctx* c, const double* ux, const double* uy) {
+  return setvel_impl<float>(c, ux, uy);
+}
 int to_f64_f32(lbm2p_ctx* c, const void* src, double* dst) {
   to_f64<float>(c, src, dst);
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;

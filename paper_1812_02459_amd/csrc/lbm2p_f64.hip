@@ -19,6 +19,9 @@ int resid_f64(lbm2p_ctx* c, double* out) { return resid_impl<double>(c, out); }
 int state_f64(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
   return state_impl<double>(c, f, g, u, set);
 }
+int setvel_f64(lbm2p_ctx* c, const double* ux, const double* uy) {
+  return setvel_impl<double>(c, ux, uy);
+}
 int to_f64_f64(lbm2p_ctx* c, const void* src, double* dst) {
   to_f64<double>(c, src, dst);
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;

@@ -685,13 +685,18 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       }
       c->uo = 1 - c->uo;
     } else {
+      // the prescribed velocity; d_t u from the one the last step used when
+      // lbm2p_set_velocity replaced it since (R18 of the oracle's readings)
       T* ux = (T*)c->U[0][0];
       T* uy = (T*)c->U[0][1];
+      T* uox = (T*)c->U[c->vpend ? 1 : 0][0];
+      T* uoy = (T*)c->U[c->vpend ? 1 : 0][1];
       ProfScope ps(c, PASS_COLLIDE);
       if (stream)
-        launch_collide<T, false, true>(c, K, par, st, Af, Ag, phi, nullptr, ux, uy, ux, uy);
+        launch_collide<T, false, true>(c, K, par, st, Af, Ag, phi, nullptr, ux, uy, uox, uoy);
       else
-        launch_collide<T, false, false>(c, K, par, st, Af, Ag, phi, nullptr, ux, uy, ux, uy);
+        launch_collide<T, false, false>(c, K, par, st, Af, Ag, phi, nullptr, ux, uy, uox, uoy);
+      c->vpend = 0;
     }
     c->parity ^= 1;
     c->steps++;
@@ -719,6 +724,7 @@ int init_impl(lbm2p_ctx* c, const double* phi0, const double* ux0, const double*
                                                    c->p.coupled ? (T*)c->pt : (T*)c->phi2, ux, uy,
                                                    c->p.coupled);
   c->uo = 0;
+  c->vpend = 0;
   c->parity = 0;
   c->steps = 0;
   c->inited = 1;
@@ -828,6 +834,7 @@ int state_impl(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
     c->from_init = 0;
     c->adj_ready = 0;
     c->res_valid = 0;
+    c->vpend = 0;
   }
   if (f) k_state<T><<<blocks1d(c->n), 256, 0, c->stream>>>(K, (T*)c->Af, f, c->parity, set, 0.0);
   if (g && c->p.coupled)
@@ -843,6 +850,23 @@ int state_impl(lbm2p_ctx* c, double* f, double* g, double* u, int set) {
                                                            c->n);
     }
   }
+  return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
+}
+
+// CH-only mode: the prescribed velocity of the following steps into U[0];
+// the velocity the last step used is kept in U[1] for the next step's d_t u
+template <typename T>
+int setvel_impl(lbm2p_ctx* c, const double* ux, const double* uy) {
+  const long long n = c->n;
+  if (!c->vpend) {
+    k_copy<T><<<blocks1d(n), 256, 0, c->stream>>>((const T*)c->U[0][0], (T*)c->U[1][0], n);
+    k_copy<T><<<blocks1d(n), 256, 0, c->stream>>>((const T*)c->U[0][1], (T*)c->U[1][1], n);
+  }
+  k_from_f64<T><<<blocks1d(n), 256, 0, c->stream>>>(ux, (T*)c->U[0][0], n);
+  k_from_f64<T><<<blocks1d(n), 256, 0, c->stream>>>(uy, (T*)c->U[0][1], n);
+  c->vpend = 1;
+  c->from_init = 0;
+  c->adj_ready = 0;
   return hipGetLastError() == hipSuccess ? LBM2P_OK : LBM2P_EHIP;
 }
 

@@ -120,6 +120,18 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
         B.lbm2p_pressure_jump(ctx)                         # no pressure in CH-only mode
     with pytest.raises(B.LBMError, match="invalid argument"):
         B.lbm2p_residual(ctx)                              # no velocity iteration either
+    with pytest.raises(B.LBMError, match="call out of order"):
+        B.lbm2p_set_velocity(ctx, base := 1 << 20, base)   # before init
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_set_velocity(ctx, None, 1 << 20)
+    B.lbm2p_destroy(ctx)
+    cp = B.make_params(ok, 0)
+    need = B.lbm2p_workspace_bytes(cp)
+    buf = ctypes.create_string_buffer(need + 512)
+    aligned = (ctypes.addressof(buf) + 255) // 256 * 256
+    ctx = B.lbm2p_create(cp, aligned, need, None)
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_set_velocity(ctx, 1 << 20, 1 << 20)        # coupled: u solves Eq:u
     B.lbm2p_destroy(ctx)
 
 

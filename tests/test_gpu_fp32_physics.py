@@ -61,10 +61,10 @@ def _run(wl, precision, steps, every=None, probe=None):
     return m, v, hist
 
 
-@pytest.mark.parametrize("seed", [1, 4])
-def test_droplet_fp32_vs_fp64_and_laplace(seed):
-    wl = I.droplet(n=200, seed=seed, steps=20000)
-    R = wl.meta["R"]
+@pytest.mark.parametrize("R", [20, 25, 30, 35, 40])
+def test_droplet_fp32_vs_fp64_and_laplace(R):
+    wl = I.droplet(n=200, seed=R, steps=20000, radii=(float(R),))
+    assert wl.meta["R"] == R
     sigma = wl.params["sigma"]
     m64, v64, _ = _run(wl, 0, 20000)
     m32, v32, _ = _run(wl, 1, 20000)
@@ -79,7 +79,7 @@ def test_droplet_fp32_vs_fp64_and_laplace(seed):
                phi_L2_rel=l2, spurious_u64=umax(m64), spurious_u32=umax(m32), spurious_rel=du,
                dp_rel=ddp, volume64=v64["count"], volume32=v32["count"],
                volume0=int((wl.phi0 > 0).sum()))
-    _record(f"droplet_seed{seed}", rec)
+    _record(f"droplet_R{R}", rec)
     assert v64["finite"] and v32["finite"]
     assert abs(dp64 / (sigma / R) - 1) < 0.05
     assert l2 <= 1e-3 and du <= 5e-2 and ddp <= 1e-3

@@ -236,10 +236,19 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
   int rd[9];
   slots<PAR>(P, x, y, rd);
-  T s = pop_ld<PAR, STREAM>(Af + rd[0]);
+  if constexpr (std::is_same<T, float>::value) {
+    // FP32: the eight moving populations (|f_i| << 1) summed first, f_0 ~ phi
+    // added last, so that the sum rounds once at phi's magnitude
+    T f[9];
 #pragma unroll
-  for (int i = 1; i < 9; ++i) s = s + pop_ld<PAR, STREAM>(Af + rd[i]);
-  phibar[id] = s;
+    for (int i = 0; i < 9; ++i) f[i] = pop_ld<PAR, STREAM>(Af + rd[i]);
+    phibar[id] = f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+  } else {
+    T s = pop_ld<PAR, STREAM>(Af + rd[0]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) s = s + pop_ld<PAR, STREAM>(Af + rd[i]);
+    phibar[id] = s;
+  }
   if (!COUPLED) return;
   T g[9];
 #pragma unroll
@@ -247,7 +256,10 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   T sg = g[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) sg = sg + g[i];
-  praw[id] = divk<3>(sg) + P.p_ref;   // sum_i 3 w_i p_ref / 3 = p_ref
+  // FP32: the correctly rounded sg / 3 (sg times the rounded 1/3 would scale p
+  // by 1 + 3e-8 every step, a drift the collision carries forward)
+  if constexpr (std::is_same<T, float>::value) praw[id] = div3_rn(sg) + P.p_ref;
+  else praw[id] = divk<3>(sg) + P.p_ref;   // sum_i 3 w_i p_ref / 3 = p_ref
   T ax = g[1];
   ax = ax - g[3];
   ax = ax + g[5];
@@ -322,6 +334,13 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
     T r;
     if (STAGE == 1) {
       r = pin + L;
+    } else if constexpr (std::is_same<T, float>::value) {
+      // FP32: eq:TVD-3order as increments of phi_bar, phi^(2) = phi_bar +
+      // (phi^(1) - phi_bar + L)/4 and phi = phi_bar + 2 (phi^(2) - phi_bar + L)/3,
+      // so that the stage rounds once at phi's magnitude (phi_bar / 3 with the
+      // rounded 1/3 would also scale phi by 1 + 3e-8 every step)
+      const T pb = phibar[id];
+      r = STAGE == 2 ? pb + T(0.25) * ((pin - pb) + L) : pb + divk<3>(T(2) * ((pin - pb) + L));
     } else if (STAGE == 2) {
       r = T(0.75) * phibar[id] + T(0.25) * (pin + L);
     } else {

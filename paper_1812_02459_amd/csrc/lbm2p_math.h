@@ -43,6 +43,16 @@ __device__ __forceinline__ T divk(T a) {
   else return div_by(a, double(C), 1.0 / C);
 }
 
+// FP32 a / 3 correctly rounded: q = RN(a RN(1/3)) is within one ulp, the
+// remainder a - 3 q is exact (one FMA), q + r RN(1/3) rounds to the nearest
+// (the FP32 case of the correction div_by applies in FP64)
+__device__ __forceinline__ float div3_rn(float a) {
+  const float y = 1.0f / 3.0f;
+  const float q = a * y;
+  const float r = __builtin_fmaf(-3.0f, q, a);
+  return __builtin_fmaf(r, y, q);
+}
+
 // eq:D2Q9: c_0 = 0, c_1..4 = axes counter-clockwise from +x, c_5..8 diagonals.
 __host__ __device__ constexpr int cx_of(int i) {
   return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);

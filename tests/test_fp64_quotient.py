@@ -5,7 +5,8 @@ Markstein's theorem makes the correctly rounded a / b for normal quotients;
 the FP64 parity with the oracle's plain divisions rests on it.  Emulated here
 exactly (rational arithmetic, one rounding per operation) against IEEE
 division, on random operands over the whole exponent range and on structured
-ones (small integers, significands next to 1 and 2, powers of two)."""
+ones (small integers, significands next to 1 and 2, powers of two).  The FP32
+kernels divide sums by 3 the same way (binary32 with fmaf), pinned likewise."""
 
 import random
 from fractions import Fraction
@@ -42,3 +43,44 @@ def test_a_planted_error_is_caught():
     rng = random.Random(5)
     cases = [rng.uniform(1, 2) * 2.0 ** rng.randint(-50, 50) for _ in range(2000)]
     assert any(a * y != a / 12.0 for a in cases)
+
+
+def _f32(x):
+    import numpy as np
+    return float(np.float32(x))
+
+
+def _fma32(x, y, z):
+    """fmaf: the exact x y + z rounded once to binary32 (Fraction to float64 is
+    exact here: x y + z of binary32 operands has at most 49 significant bits
+    within a small exponent range, so the float64 value rounds once to binary32)."""
+    import numpy as np
+    v = Fraction(x) * Fraction(y) + Fraction(z)
+    d = float(v)
+    assert Fraction(d) == v
+    return float(np.float32(d))
+
+
+def test_fp32_division_by_three_is_correctly_rounded():
+    """The FP32 gather's p = c_s^2 sum g as q = RN(a RN(1/3)), r = fmaf(-3, q, a),
+    q' = fmaf(r, RN(1/3), q): correctly rounded a / 3 (the plain product is off by
+    an ulp with a bias, which a step carries forward)."""
+    import numpy as np
+    y = _f32(1.0 / 3.0)
+    rng = random.Random(33)
+    cases = [_f32(rng.uniform(1, 2) * 2.0 ** rng.randint(-60, 60)) for _ in range(6000)]
+    cases += [_f32(1.0 + k * 2.0 ** -23) for k in range(2000)]
+    cases += [_f32(2.0 - k * 2.0 ** -23) for k in range(1, 2000)]
+    cases += [float(i) for i in range(1, 2000)]
+    bad, plain_off = [], 0
+    for a in cases:
+        for s in (a, -a):
+            q = _f32(s * y)
+            r = _fma32(-3.0, q, s)
+            out = _fma32(r, y, q)
+            exact = float(np.float32(Fraction(s) / 3))
+            if out != exact:
+                bad.append(s)
+            plain_off += q != exact
+    assert not bad, bad[:5]
+    assert plain_off > 0

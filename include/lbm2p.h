@@ -150,6 +150,25 @@ int lbm2p_fields(lbm2p_ctx* c, int32_t which, double* d_out);
  * Returns ENONFINITE if sum phi or max|u~| is not finite. */
 int lbm2p_volume(lbm2p_ctx* c, double out[6]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops, harnesses that forbid allocation): the diagnostics
+ * of lbm2p_volume on device float64 planes [ny][nx] the caller passes, with no
+ * context and no workspace.  d_p may be NULL (out[2] = 0); d_out: device
+ * memory for 6 doubles, the values of lbm2p_volume in its order (and bitwise
+ * equal to them for the planes lbm2p_moments reports).  Asynchronous on
+ * stream (NULL: the null stream); nothing is checked for finiteness (out[1]
+ * and out[3] are NaN or Inf for a non-finite state).  The per-workgroup
+ * partials live in a static array of the library, 64 KiB on each device that
+ * calls it, held until the process ends; it allocates nothing.  Every call on
+ * one device shares that array, so calls that overlap on one device (on
+ * different streams or threads) race; every partial is written before it is
+ * read, so nothing needs clearing between calls.  EINVAL for a NULL plane or
+ * output, nx or ny < 1, or more than 2^31 - 1 nodes; EHIP when the device
+ * array cannot be located or a launch fails. */
+int lbm2p_volume_noalloc(const double* d_phi, const double* d_p, const double* d_ux,
+                         const double* d_uy, int32_t nx, int32_t ny, double* d_out,
+                         void* stream);
+
 /* Rising-bubble diagnostics of Sec. 4.5 (eq:quantify-yc, eq:quantify-uc) over
  * the nodes with phi < 0 (the light phase): out[0] their number, out[1] their
  * mean row index y_c (the node of row j sits at y = j; a wall in y lies half a

@@ -86,6 +86,7 @@ _sig = {
     "lbm2p_track_residual": [_vp, ctypes.c_int32],
     "lbm2p_residual": [_vp, ctypes.POINTER(ctypes.c_double)],
     "lbm2p_set_velocity": [_vp, _vp, _vp],
+    "lbm2p_volume_noalloc": [_vp, _vp, _vp, _vp, ctypes.c_int32, ctypes.c_int32, _vp, _vp],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -176,6 +177,11 @@ def lbm2p_volume(ctx):
     if code not in (OK, ENONFINITE):
         _check(code, "lbm2p_volume")
     return code, list(out)
+
+
+def lbm2p_volume_noalloc(phi, p, ux, uy, nx, ny, out, stream_ptr):
+    _check(_lib.lbm2p_volume_noalloc(_vp(phi), _vp(p), _vp(ux), _vp(uy), int(nx), int(ny),
+                                     _vp(out), _vp(stream_ptr)), "lbm2p_volume_noalloc")
 
 
 def lbm2p_bubble(ctx):

@@ -419,6 +419,15 @@ int lbm2p_volume(lbm2p_ctx* c, double out[6]) {
   return c->prec ? volume_f32(c, out) : volume_f64(c, out);
 }
 
+int lbm2p_volume_noalloc(const double* d_phi, const double* d_p, const double* d_ux,
+                         const double* d_uy, int32_t nx, int32_t ny, double* d_out,
+                         void* stream) {
+  if (!d_phi || !d_ux || !d_uy || !d_out || nx < 1 || ny < 1) return LBM2P_EINVAL;
+  if ((long long)nx * ny > (long long)INT32_MAX) return LBM2P_EINVAL;
+  return volume_noalloc_f64(d_phi, d_p, d_ux, d_uy, (long long)nx * ny, d_out,
+                            (hipStream_t)stream);
+}
+
 int lbm2p_bubble(lbm2p_ctx* c, double out[3]) {
   if (!c || !out) return LBM2P_EINVAL;
   if (!c->inited) return LBM2P_ESTATE;

@@ -128,4 +128,9 @@ LBM2P_DECLARE(f64)
 LBM2P_DECLARE(f32)
 #undef LBM2P_DECLARE
 
+// the diagnostics of lbm2p_volume on float64 planes, partials in the FP64
+// unit's static scratch (lbm2p_volume_noalloc)
+int volume_noalloc_f64(const double* phi, const double* p, const double* ux, const double* uy,
+                       long long n, double* out, hipStream_t stream);
+
 }  // namespace lbm2p

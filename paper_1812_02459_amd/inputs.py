@@ -79,6 +79,39 @@ def vortex(n=128, U=0.05, steps=1000):
                     dict(R=R, U=U))
 
 
+def vortex_modulated(L=400, U0=0.02, n_period=2, eta=2.0, lam=0.05, sigma=1e-3, R_frac=0.15,
+                     eps=1e-2):
+    """Single-vortex deformation as Sec. 4.1 sets it up (eq:velocity): L x L
+    periodic, CH only, a circle of radius R_frac L at (0.5L, 0.75L) (the radius
+    is not stated; 0.15 L as in the problem the section reproduces), the base
+    field u0 = U0 sin^2(pi x) sin(2 pi y), v0 = -U0 sin^2(pi y) sin(2 pi x) with
+    x = i/L, y = j/L, modulated by cos(pi t/T), T = n L/U0 (meta["T"]); the
+    caller prescribes u0 cos(pi t/T) before each step.  eta = 2 with tau_f =
+    1/2 + sqrt(3)/6 gives M = eta c_s^2 (tau_f - 1/2) (eq:mobility)."""
+    phi = drop_field(L, L, 0.5 * L, 0.75 * L, R_frac * L, 4.0, inside=1.0)
+    x, y = _grid(L, L)
+    xs, ys = x / L, y / L
+    ux = U0 * np.sin(np.pi * xs) ** 2 * np.sin(2 * np.pi * ys)
+    uy = -U0 * np.sin(np.pi * ys) ** 2 * np.sin(2 * np.pi * xs)
+    M = eta * (TAU_F - 0.5) / 3.0
+    T = n_period * L / U0
+    prm = base_params(L, L, coupled=False, sigma=sigma, lam=lam, M=M, filter_n=0, eps=eps)
+    return Workload("vortex_modulated", prm, phi, ux, uy, np.zeros_like(phi),
+                    int(round(2 * T)), dict(T=T, U0=U0, R=R_frac * L))
+
+
+def table3_droplet(R=20.0, L=200, original_ch=False, steps=200000, eps=1e-2):
+    """The volume test after the Laplace test (Sec. 4.3, Table III): a droplet of
+    radius R at the centre of an L x L periodic box, rho1/rho2 = 10/1,
+    sigma = 1e-3, tau_f = 0.6 (as printed); the viscosities are not printed:
+    nu = 0.01 in both phases; lambda = 0.005, M = 0.02, W = 4, SF-11."""
+    phi = drop_field(L, L, 0.5 * L, 0.5 * L, R, 4.0, inside=1.0)
+    z = np.zeros_like(phi)
+    prm = base_params(L, L, rho1=10.0, rho2=1.0, mu1=0.1, mu2=0.01, sigma=1e-3, tau_f=0.6,
+                      original_ch=original_ch, eps=eps)
+    return Workload("table3_droplet", prm, phi, z, z.copy(), z.copy(), steps, dict(R=R))
+
+
 def translating_drop(L=100, U=0.01, lam=0.005, sigma=0.01, steps=4000, R=26.0, W=4.0):
     """Circular drop carried by a uniform velocity (Sec. "Effect of parameter
     lambda"): CH-only on a 3L x L periodic domain (the paper's L x 3L with the

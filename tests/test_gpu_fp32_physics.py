@@ -189,24 +189,34 @@ def test_translating_drop_lambda_tables():
     more than the tiny deviation the paper reports there (its largest entry at
     lambda = 0.01 is 0.00168; measured here <= 1.4e-4; the paper also notes
     the error stops decreasing, and the first run of this check, which asked
-    for no rise from 0.005 to 0.01, read 7.9e-5 -> 1.3e-4)."""
+    for no rise from 0.005 to 0.01, read 7.9e-5 -> 1.3e-4).  The lambda = 0
+    column is the original CH method, as the section names it (reading R19:
+    no FD sub-step at all); lambda = 0 with the FD sub-step (the flux
+    correction q alone) is printed beside it."""
     from paper_1812_02459_amd.binding import Sim
-    rows = {}
+
+    def run(wl, **kw):
+        sim = Sim(dict(wl.params, **kw), precision=0)
+        sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
+        sim.step(wl.steps)
+        ph = sim.moments()["phi"].cpu().numpy()
+        sim.close()
+        return A.overshoots(ph) if np.isfinite(ph).all() else (float("nan"),) * 2
+
+    rows, q_only = {}, {}
     for (U, sig), paper in _PAPER_MAX.items():
         got = []
         for lam in _LAMBDAS:
             wl = I.translating_drop(L=100, U=U, lam=lam, sigma=sig, steps=4000)
-            sim = Sim(wl.params, precision=0)
-            sim.init(wl.phi0, wl.ux0, wl.uy0, wl.p0)
-            sim.step(wl.steps)
-            ph = sim.moments()["phi"].cpu().numpy()
-            sim.close()
-            got.append(A.overshoots(ph) if np.isfinite(ph).all() else (float("nan"),) * 2)
+            got.append(run(wl, original_ch=(lam == 0.0)))
+        q_only[(U, sig)] = run(I.translating_drop(L=100, U=U, lam=0.0, sigma=sig, steps=4000))
         rows[(U, sig)] = got
         print(f"U={U} sigma={sig}: lambda -> (max, min) overshoot, paper max:",
               [(lam, "%.5f" % g[0], "%.5f" % g[1], p) for lam, g, p in zip(_LAMBDAS, got, paper)],
-              flush=True)
+              "| lambda = 0 with the FD sub-step: %.5f %.5f" % q_only[(U, sig)], flush=True)
     _record("translating_drop", {f"U={U},sigma={s}": v for (U, s), v in rows.items()})
+    _record("translating_drop_lambda0_with_fd", {f"U={U},sigma={s}": v
+                                                 for (U, s), v in q_only.items()})
     for key, got in rows.items():
         m = [max(g) for g in got]
         assert m[0] > 0.03, (key, m)

@@ -69,6 +69,20 @@ R18 CH-only mode (prescribed velocity, no hydrodynamics): u~ = the prescribed u;
     d_t u in eq:Fi is the backward difference of the prescribed velocities of
     consecutive steps (R12's difference), 0 for a velocity held fixed.
 R19 "original CH" (Sec. 4.1-4.3 comparisons, lambda = 0) means no FD sub-step at all.
+R20 strain rate from the moments (eq:Fmu, an option; R9 is the default).  The
+    printed formula is garbled (f for g; F for the F - grad p of eq:Gi) and is
+    re-derived here from App. A's first-order balances of m_1, m_7 and m_8
+    (eq:t2momentum_auxilliary, with d_t1 p = -c_s^2 div u and d_t1 u = b + O(u^2),
+    b = F/rho - grad p per R8): with A_k = m_k(g) - m_k^eq + G~_k/2 of the
+    pre-collision g,
+        div u = -(s_1/2) A_1,  d_x u_x - d_y u_y = -(3/2) s_7 A_7,
+        d_x u_y + d_y u_x = -3 s_8 A_8,
+    m_1^eq = -6p + 3|u|^2, m_7^eq = u_x^2 - u_y^2, m_8^eq = u_x u_y,
+    G~_1/2 = 3 b.u, G~_7/2 = b_x u_x - b_y u_y, G~_8/2 = (b_x u_y + b_y u_x)/2.
+    Inside F the strain rate enters F_nu itself, so the b of these corrections
+    is the one of the other force parts (F - F_nu)/rho - grad p (with R21:
+    (F - F_nu - grad p)/rho).
+R21 literal eq:Gi (an option for the study of R8): b = (F - grad p)/rho.
 """
 
 import dataclasses
@@ -112,6 +126,8 @@ class Params:
     s_g: tuple = (1.0, 1.0, 1.0, 1.0, 1.0, 1.0, 1.0, None, None)
     eps: float = 1e-2             # |grad phi| regularisation (R2)
     original_ch: bool = False     # no FD sub-step: the original convective CH (Sec. 4.2)
+    strain_moments: bool = False  # F_nu's strain rate from the moments of g (R20, eq:Fmu)
+    gi_literal: bool = False      # eq:Gi as printed, b = (F - grad p)/rho (R21)
 
     # derived constants, Sec. 2.1 and eq:mobility
     @property
@@ -353,11 +369,27 @@ def properties(ph, prm):
     return rho, muv / rho
 
 
-def forces(phi, p, ux, uy, prm):
+def strain_from_moments(g, p, ux, uy, bx, by, nu, prm):
+    """grad u + grad u^T from the non-equilibrium moments of the pre-collision g
+    (eq:Fmu as re-derived in R20); returns (S_xx, S_xy, S_yy)."""
+    m = m_apply(g)
+    s1 = prm.s_g[1]
+    s7 = 1.0 / (nu * 3.0 + 0.5)                 # s_7 = s_8 = 1/tau_g (eq:dynamic_vis)
+    A1 = (m[1] - ((-6.0) * p + 3.0 * (ux * ux + uy * uy))) + 3.0 * (bx * ux + by * uy)
+    A7 = (m[7] - (ux * ux - uy * uy)) + (bx * ux - by * uy)
+    A8 = (m[8] - ux * uy) + 0.5 * (bx * uy + by * ux)
+    div = (-0.5 * s1) * A1
+    D = (-1.5 * s7) * A7
+    return div + D, (-3.0 * s7) * A8, div - D
+
+
+def forces(phi, p, ux, uy, prm, g=None):
     """F = F_p + F_s + F_nu + F_m + F_g (eq:reformNS, eq:surfaceforce, Sec. 2.2).
 
     phi: order parameter (no halo), p: pressure (no halo), ux/uy: velocity
     (no halo).  Returns a dict with F, rho, nu, grad u and mu_phi at the nodes.
+    With prm.strain_moments, the strain rate of F_nu comes from the moments of
+    the pre-collision populations g (R20) instead of the velocity's stencil.
     """
     wx, wy = prm.wall_x, prm.wall_y
     P2 = ext(phi, 2, wx, wy)
@@ -384,15 +416,27 @@ def forces(phi, p, ux, uy, prm):
     duyx, duyy = iso_grad(U1y)
     Fpx = -p * grx
     Fpy = -p * gry
-    Sxx = duxx + duxx
-    Sxy = duyx + duxy
-    Syy = duyy + duyy
-    Fnx = nu * (Sxx * grx + Sxy * gry)
-    Fny = nu * (Sxy * grx + Syy * gry)
     Fmx = Jx * duxx + Jy * duxy
     Fmy = Jx * duyx + Jy * duyy
     Fgx = (rho - prm.rho_ref) * prm.gx
     Fgy = (rho - prm.rho_ref) * prm.gy
+    if prm.strain_moments and g is not None:
+        dpx, dpy = iso_grad(ext(p, 1, wx, wy))
+        Frx = ((Fpx + Fsx) + Fmx) + Fgx
+        Fry = ((Fpy + Fsy) + Fmy) + Fgy
+        if prm.gi_literal:
+            brx = (Frx - dpx) / rho
+            bry = (Fry - dpy) / rho
+        else:
+            brx = Frx / rho - dpx
+            bry = Fry / rho - dpy
+        Sxx, Sxy, Syy = strain_from_moments(g, p, ux, uy, brx, bry, nu, prm)
+    else:
+        Sxx = duxx + duxx
+        Sxy = duyx + duxy
+        Syy = duyy + duyy
+    Fnx = nu * (Sxx * grx + Sxy * gry)
+    Fny = nu * (Sxy * grx + Syy * gry)
     Fx = (((Fpx + Fsx) + Fnx) + Fmx) + Fgx
     Fy = (((Fpy + Fsy) + Fny) + Fmy) + Fgy
     return dict(Fx=Fx, Fy=Fy, rho=rho, nu=nu, mu=mup[1:-1, 1:-1], Jx=Jx, Jy=Jy,
@@ -400,12 +444,13 @@ def forces(phi, p, ux, uy, prm):
                 duxx=duxx, duxy=duxy, duyx=duyx, duyy=duyy)
 
 
-def velocity_iteration(phi, praw, jx, jy, u0x, u0y, prm):
-    """u = sum g c + F(u) dt/(2 rho) (Eq:u), solved by K fixed-point sweeps (R10)."""
+def velocity_iteration(phi, praw, jx, jy, u0x, u0y, prm, g=None):
+    """u = sum g c + F(u) dt/(2 rho) (Eq:u), solved by K fixed-point sweeps (R10);
+    g: the pre-collision populations (the strain rate of R20)."""
     ux, uy = u0x, u0y
     prevx, prevy = ux, uy
     for _ in range(prm.K):
-        fr = forces(phi, praw, ux, uy, prm)
+        fr = forces(phi, praw, ux, uy, prm, g=g)
         prevx, prevy = ux, uy
         ux = jx + fr["Fx"] / (2 * fr["rho"])
         uy = jy + fr["Fy"] / (2 * fr["rho"])
@@ -468,11 +513,15 @@ def collide(f, g, phi, p, ux, uy, uox, uoy, prm):
     fst = mrt_collide(f, f_eq(phi, mu, ux, uy, prm), src_f(phi, ax, ay), _s_f(prm))
     if g is None:
         return fst, None
-    fr = forces(phi, p, ux, uy, prm)
+    fr = forces(phi, p, ux, uy, prm, g=g)
     dpx, dpy = iso_grad(ext(p, 1, wx, wy))
     rho = fr["rho"]
-    bx = fr["Fx"] / rho - dpx
-    by = fr["Fy"] / rho - dpy
+    if prm.gi_literal:
+        bx = (fr["Fx"] - dpx) / rho
+        by = (fr["Fy"] - dpy) / rho
+    else:
+        bx = fr["Fx"] / rho - dpx
+        by = fr["Fy"] / rho - dpy
     gst = mrt_collide(g, g_eq(p, ux, uy),
                       src_g(fr["Fx"], fr["Fy"], rho, ux, uy, bx, by),
                       _s_g(prm, fr["nu"]))
@@ -509,7 +558,7 @@ def step(st, prm):
         fst, _ = collide(f, None, phi, None, uox, uoy, prev[0], prev[1], prm)
         return State(fs=torch.stack(fst), gs=None, uo=st.uo, n=st.n + 1,
                      phi=phi, phibar=phibar)
-    uKx, uKy, resid = velocity_iteration(phi, praw, jx, jy, uox, uoy, prm)
+    uKx, uKy, resid = velocity_iteration(phi, praw, jx, jy, uox, uoy, prm, g=g)
     pt, utx, uty = filter_fields(praw, uKx, uKy, prm)
     fst, gst = collide(f, g, phi, pt, utx, uty, uox, uoy, prm)
     return State(fs=torch.stack(fst), gs=torch.stack(gst), uo=torch.stack([utx, uty]),

@@ -70,7 +70,7 @@ def test_planted_sign_error_in_a_force_term_is_caught():
     L = _loss(fs, st.gs, st.uo, dataclasses.replace(prm, sigma=sig), cot)
     (g_true,) = torch.autograd.grad(L, [sig])
     # planted mistake: the surface-force contribution enters with the wrong sign
-    S.forces = lambda phi, p, ux, uy, prm_: _flip_fs(orig, phi, p, ux, uy, prm_)
+    S.forces = lambda phi, p, ux, uy, prm_, g=None: _flip_fs(orig, phi, p, ux, uy, prm_, g=g)
     try:
         sig2 = torch.tensor(prm.sigma, dtype=torch.float64, requires_grad=True)
         L2 = _loss(fs, st.gs, st.uo, dataclasses.replace(prm, sigma=sig2), cot)
@@ -80,11 +80,11 @@ def test_planted_sign_error_in_a_force_term_is_caught():
     assert abs(float(g_bad) - float(g_true)) > 1e-6 * abs(float(g_true))
 
 
-def _flip_fs(orig, phi, p, ux, uy, prm):
+def _flip_fs(orig, phi, p, ux, uy, prm, g=None):
     """forces() with the surface force's sign reversed (planted mistake)."""
-    d = dict(orig(phi, p, ux, uy, prm))
+    d = dict(orig(phi, p, ux, uy, prm, g=g))
     z = dataclasses.replace(prm, sigma=0.0 * prm.sigma)
-    d0 = orig(phi, p, ux, uy, z)
+    d0 = orig(phi, p, ux, uy, z, g=g)
     # F(sigma) - F(0) is the sigma-dependent part (F_s plus J's mu terms)
     d["Fx"] = d0["Fx"] - (d["Fx"] - d0["Fx"])
     d["Fy"] = d0["Fy"] - (d["Fy"] - d0["Fy"])

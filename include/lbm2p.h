@@ -55,6 +55,8 @@ enum {
   LBM2P_ESTATE = 5       /* call out of order (e.g. step before init)      */
 };
 
+enum { LBM2P_OPT_STRAIN_MOMENTS = 1, LBM2P_OPT_GI_LITERAL = 2 };
+
 /* Parameters.  Phase phi = +1 has density rho1 and dynamic viscosity mu1,
  * phase phi = -1 has rho2, mu2 (eq:rho, eq:dynamic_vis).  Lattice units,
  * dx = dt = 1 (Sec. 3.1). */
@@ -85,7 +87,14 @@ typedef struct lbm2p_params {
   double s_g[9];           /* MRT rates of g; entries 7, 8 are 1/tau_g(x)      */
   double eps;              /* regularisation of |grad phi| in n, >= 0          */
   int32_t original_ch;     /* 1 = no FD sub-step (the original convective CH)  */
-  int32_t reserved;        /* must be 0                                        */
+  int32_t options;         /* bit flags, 0 = the default readings:
+                              LBM2P_OPT_STRAIN_MOMENTS: the strain rate of F_nu
+                              from the non-equilibrium moments of g (eq:Fmu,
+                              re-derived from App. A) instead of the velocity's
+                              isotropic stencil;
+                              LBM2P_OPT_GI_LITERAL: eq:Gi as printed,
+                              u (F - grad p) / rho, instead of u (F/rho - grad p);
+                              neither has an adjoint (lbm2p_record: EINVAL)     */
   double p_ref;            /* reference kinematic pressure of the stored g:
                               the library keeps g_i - 3 w_i p_ref, deviations
                               from the lattice weights (the state I/O converts;
@@ -106,7 +115,8 @@ int lbm2p_workspace_bytes(const lbm2p_params* p, size_t* bytes);
  * order not in {0,5,7,9,11}, compact_n outside 1..5, |compact_alpha| >= 1/2,
  * a compact filter on a lattice side above 7680 (its line solve holds a line in LDS),
  * K outside 1..8, filter_a outside [0,1], eps < 0, a wall axis shorter than the
- * ghost depth; ENOSPACE for a small workspace; EHIP if an event cannot be made. */
+ * ghost depth, unknown option bits (or any option in CH-only mode); ENOSPACE for a
+ * small workspace; EHIP if an event cannot be made. */
 int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes,
                  void* stream, lbm2p_ctx** out);
 
@@ -241,7 +251,7 @@ int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t
  * 256-byte aligned, >= the bytes above, owned by the caller and kept alive
  * until the last lbm2p_adjoint of this record returns or the next record).
  * ESTATE before init or right after lbm2p_set_velocity (see there); EINVAL for
- * invalid values; ENOSPACE for a small d_ws. */
+ * invalid values or a context with options set; ENOSPACE for a small d_ws. */
 int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes);
 
 /* Inputs (seeds) and outputs of lbm2p_adjoint.  Device float64 arrays in the

@@ -25,6 +25,7 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOSPACE, EHIP, ENONFINITE, ESTATE = range(6)
+OPT_STRAIN_MOMENTS, OPT_GI_LITERAL = 1, 2
 PASSES = {"gather": 0, "fd": 1, "vel": 2, "filter": 3, "collide": 4}
 FIELDS = {"phibar": 0, "praw": 1, "jx": 2, "jy": 3, "uKx": 4, "uKy": 5, "phi1": 6, "phi2": 7}
 
@@ -44,7 +45,7 @@ class Params(ctypes.Structure):
         ("filter_a", ctypes.c_double), ("compact_alpha", ctypes.c_double),
         ("s_f", ctypes.c_double * 9), ("s_g", ctypes.c_double * 9),
         ("eps", ctypes.c_double),
-        ("original_ch", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("original_ch", ctypes.c_int32), ("options", ctypes.c_int32),
         ("p_ref", ctypes.c_double),
     ]
 
@@ -130,7 +131,8 @@ def make_params(d, precision=0):
         p.s_f[k] = 0.0 if sf[k] is None else float(sf[k])
         p.s_g[k] = 0.0 if sg[k] is None else float(sg[k])
     p.original_ch = int(bool(d.get("original_ch", False)))
-    p.reserved = 0
+    p.options = (OPT_STRAIN_MOMENTS if d.get("strain_moments", False) else 0) | \
+        (OPT_GI_LITERAL if d.get("gi_literal", False) else 0)
     p.p_ref = float(d.get("p_ref", 0.0))
     return p
 

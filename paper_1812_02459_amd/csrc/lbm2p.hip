@@ -44,7 +44,8 @@ int validate(const lbm2p_params* p) {
   if (p->K < 1 || p->K > 8) return LBM2P_EINVAL;
   if (!(p->filter_a >= 0 && p->filter_a <= 1)) return LBM2P_EINVAL;
   if (p->coupled != 0 && p->coupled != 1) return LBM2P_EINVAL;
-  if (p->reserved != 0) return LBM2P_EINVAL;
+  if (p->options & ~(LBM2P_OPT_STRAIN_MOMENTS | LBM2P_OPT_GI_LITERAL)) return LBM2P_EINVAL;
+  if (p->options && !p->coupled) return LBM2P_EINVAL;
   if (!std::isfinite(p->p_ref)) return LBM2P_EINVAL;
   return LBM2P_OK;
 }
@@ -55,7 +56,9 @@ long long plane_stride(const lbm2p_params* p) {
 
 size_t n_planes(const lbm2p_params* p) {
   // f(9) + phi, phibar, phi1, phi2 + U(4)  [+ g(9) + praw, jx, jy, pt + uk(4)]
-  return p->coupled ? 9 + 4 + 4 + 9 + 4 + 4 : 9 + 4 + 4;
+  // [+ m1, m7, m8 of the pre-collision g for the moment strain rate]
+  const size_t sm = (p->options & LBM2P_OPT_STRAIN_MOMENTS) ? 3 : 0;
+  return p->coupled ? 9 + 4 + 4 + 9 + 4 + 4 + sm : 9 + 4 + 4;
 }
 
 size_t compact_planes(const lbm2p_params* p) { return (p->coupled && p->compact) ? 6 : 0; }
@@ -255,8 +258,16 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
     c->pt = take(1);
     for (int a = 0; a < 2; ++a)
       for (int b = 0; b < 2; ++b) c->uk[a][b] = take(1);
+    if (p->options & LBM2P_OPT_STRAIN_MOMENTS) {
+      c->sm1 = take(1);
+      c->sm7 = take(1);
+      c->sm8 = take(1);
+    } else {
+      c->sm1 = c->sm7 = c->sm8 = nullptr;
+    }
   } else {
     c->Ag = c->praw = c->jx = c->jy = c->pt = nullptr;
+    c->sm1 = c->sm7 = c->sm8 = nullptr;
   }
   c->cscratch = compact_planes(p) ? take((long long)compact_planes(p)) : nullptr;
   c->red = (double*)(((uintptr_t)q + 255) & ~(uintptr_t)255);
@@ -358,6 +369,7 @@ int lbm2p_adjoint_workspace_bytes(const lbm2p_params* p, int32_t nsteps, int32_t
 
 int lbm2p_record(lbm2p_ctx* c, int32_t nsteps, int32_t ckpt_every, void* d_ws, size_t bytes) {
   if (!c || nsteps < 0 || ckpt_every < 1 || !d_ws || ((uintptr_t)d_ws & 255)) return LBM2P_EINVAL;
+  if (c->p.options) return LBM2P_EINVAL;   // the reverse step covers the default readings
   // a velocity set since the last step: that step's d_t u is not a constant of
   // the recorded run, which the reverse of the CH-only collision assumes
   if (!c->inited || c->vpend) return LBM2P_ESTATE;

@@ -18,6 +18,7 @@ struct lbm2p_ctx {
   // fields (in the context's precision)
   void *Af, *Ag, *phi, *phibar, *phi1, *phi2, *praw, *jx, *jy, *pt;
   void* uk[2][2];  // velocity iterates
+  void *sm1, *sm7, *sm8;  // moments m_1, m_7, m_8 of the pre-collision g (moment strain rate)
   void* U[2][2];   // filtered velocity, double buffered (u~^n and u~^{n+1})
   double* red;     // reduction partials (+ 8 results)
   int uo;          // index of u~^n in U

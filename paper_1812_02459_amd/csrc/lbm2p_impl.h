@@ -372,6 +372,7 @@ KParams<T> kparams(const lbm2p_ctx* c) {
     k.s_f[i] = T(c->s_f[i]);
     k.s_g[i] = T(c->s_g[i]);
   }
+  k.opt = p.options;
   return k;
 }
 
@@ -481,13 +482,13 @@ bool stream_populations(const lbm2p_ctx* c) {
 
 template <typename T, bool COUPLED, bool STREAM>
 void launch_gather(const KParams<T>& K, int par, long long n, hipStream_t st, T* Af, T* Ag,
-                   T* phibar, T* praw, T* jx, T* jy, T* m7, T* m8) {
+                   T* phibar, T* praw, T* jx, T* jy, T* m7, T* m8, T* m1 = nullptr) {
   if (par == 0)
     k_gather<T, 0, COUPLED, STREAM><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, praw, jx, jy,
-                                                                 m7, m8);
+                                                                 m7, m8, m1);
   else
     k_gather<T, 1, COUPLED, STREAM><<<blocks1d(n), 256, 0, st>>>(K, Af, Ag, phibar, praw, jx, jy,
-                                                                 m7, m8);
+                                                                 m7, m8, m1);
 }
 
 template <typename T, bool COUPLED, bool STREAM>
@@ -496,6 +497,15 @@ void launch_collide(lbm2p_ctx* c, const KParams<T>& K, int par, hipStream_t st, 
                     const T* uoy) {
   using C = StepCfg<T>;
   const Tiles<C::COL_TX, C::COL_TY> tc(c->p);
+  if (COUPLED && (K.opt & LBM2P_OPT_STRAIN_MOMENTS)) {   // the option's own instantiation
+    if (par == 0)
+      k_collide<T, 0, COUPLED, false, C::COL_TX, C::COL_TY, C::COL_NT, true>
+          <<<tc.grid(), C::COL_NT, 0, st>>>(K, tc.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
+    else
+      k_collide<T, 1, COUPLED, false, C::COL_TX, C::COL_TY, C::COL_NT, true>
+          <<<tc.grid(), C::COL_NT, 0, st>>>(K, tc.tx, Af, Ag, phi, pt, ux, uy, uox, uoy);
+    return;
+  }
   if constexpr (!STREAM) {   // small lattices (never streamed): the small tiles
     if (tc.tx * (long long)tc.ty < TINY_TILES) {
       const Tiles<C::COLT_TX, C::COLT_TY> tt(c->p);
@@ -540,9 +550,19 @@ void launch_fd(lbm2p_ctx* c, const KParams<T>& K, hipStream_t st, T* phibar, T* 
 template <typename T, int TY, int NT>
 void launch_vel(const lbm2p_params& p, const KParams<T>& K, hipStream_t st, bool two, const T* phi,
                 const T* praw, const T* jx, const T* jy, const T* ux, const T* uy, T* ox, T* oy,
-                T* o1x, T* o1y) {
+                T* o1x, T* o1y, const T* m1 = nullptr, const T* m7 = nullptr,
+                const T* m8 = nullptr) {
   constexpr int TX = StepCfg<T>::TX;
   const Tiles<TX, TY> tv(p);
+  if (m1) {   // moment strain rate: its own instantiations
+    if (two)
+      k_vel2<T, TX, TY, NT, true><<<tv.grid(), NT, 0, st>>>(K, tv.tx, phi, praw, jx, jy, ux, uy,
+                                                              ox, oy, o1x, o1y, m1, m7, m8);
+    else
+      k_vel<T, 1, TX, TY, NT, true><<<tv.grid(), NT, 0, st>>>(K, tv.tx, phi, praw, jx, jy, ux, uy,
+                                                                ox, oy, m1, m7, m8);
+    return;
+  }
   if (two)
     k_vel2<T, TX, TY, NT><<<tv.grid(), NT, 0, st>>>(K, tv.tx, phi, praw, jx, jy, ux, uy, ox, oy,
                                                     o1x, o1y);
@@ -583,14 +603,17 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       ProfScope ps(c, PASS_GATHER);
       // while recording for the adjoint, the gather also keeps m_7, m_8 of the
       // pre-collision g (the g-relaxation rate's derivative needs them)
-      T* m7 = c->rec && p.coupled ? (T*)c->rec_m7 : nullptr;
-      T* m8 = c->rec && p.coupled ? (T*)c->rec_m8 : nullptr;
+      // (with the moment strain rate it keeps m_1, m_7, m_8 for the velocity sweeps)
+      const bool sm = p.coupled && (p.options & LBM2P_OPT_STRAIN_MOMENTS);
+      T* m7 = c->rec && p.coupled ? (T*)c->rec_m7 : (sm ? (T*)c->sm7 : nullptr);
+      T* m8 = c->rec && p.coupled ? (T*)c->rec_m8 : (sm ? (T*)c->sm8 : nullptr);
+      T* m1 = sm ? (T*)c->sm1 : nullptr;
       T* praw = p.coupled ? (T*)c->praw : nullptr;
       T* jx = p.coupled ? (T*)c->jx : nullptr;
       T* jy = p.coupled ? (T*)c->jy : nullptr;
       if (p.coupled) {
-        if (stream) launch_gather<T, true, true>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
-        else launch_gather<T, true, false>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
+        if (stream) launch_gather<T, true, true>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8, m1);
+        else launch_gather<T, true, false>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8, m1);
       } else {
         if (stream) launch_gather<T, false, true>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
         else launch_gather<T, false, false>(K, par, n, st, Af, Ag, phibar, praw, jx, jy, m7, m8);
@@ -633,7 +656,12 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         T* o1x = (T*)(c->rec && two ? c->rec_uk[done][0] : nullptr);
         T* o1y = (T*)(c->rec && two ? c->rec_uk[done][1] : nullptr);
         ProfScope ps(c, PASS_VEL);
-        if (tv.tx * (long long)tv.ty < TINY_TILES)
+        if (p.options & LBM2P_OPT_STRAIN_MOMENTS)
+          launch_vel<T, C::VEL_TY, C::VEL_NT>(p, K, st, two, phi, (T*)c->praw, (T*)c->jx,
+                                              (T*)c->jy, ux, uy, ox, oy, o1x, o1y,
+                                              (const T*)c->sm1, (const T*)c->sm7,
+                                              (const T*)c->sm8);
+        else if (tv.tx * (long long)tv.ty < TINY_TILES)
           launch_vel<T, TINY_TY, TINY_NT>(
               p, K, st, two, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
         else

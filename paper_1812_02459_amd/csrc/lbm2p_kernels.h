@@ -66,6 +66,7 @@ struct KParams {
   T fd[6];                      // filter coefficients d_0..d_N
   int fn;                       // N = half width of the explicit filter
   T s_f[9], s_g[9];
+  int opt;                      // LBM2P_OPT_* bits
 };
 
 // ---------------------------------------------------------------- boundaries
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
                                                 const T* __restrict__ Ag, T* __restrict__ phibar,
                                                 T* __restrict__ praw, T* __restrict__ jx,
                                                 T* __restrict__ jy, T* __restrict__ m7,
-                                                T* __restrict__ m8) {
+                                                T* __restrict__ m8, T* __restrict__ m1) {
   const long long n = (long long)P.nx * P.ny;
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
@@ -277,6 +278,11 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   if (m7) {
     m7[id] = ((g[1] - g[2]) + g[3]) - g[4];
     m8[id] = ((g[5] - g[6]) + g[7]) - g[8];
+  }
+  if (m1) {
+    T a, b, c;
+    moments_178<T>(g, a, b, c);
+    m1[id] = a;
   }
 }
 
@@ -419,17 +425,64 @@ __device__ __forceinline__ void node_force(const Tile<T>& tP, const Tile<T>& tPx
   Fy = (((Fpy + Fsy) + Fny) + Fmy) + Fgy;
 }
 
+// F at tile node (x, y) with the strain rate of F_nu from the moments m1, m7,
+// m8 of the node's pre-collision g (LBM2P_OPT_STRAIN_MOMENTS): the other force
+// parts first, b of the source corrections from them and grad p, then F_nu
+// (summed in node_force's order)
+template <typename T>
+__device__ __forceinline__ void node_force_sm(const Tile<T>& tP, const Tile<T>& tPx,
+                                              const Tile<T>& tPy, const Tile<T>& tMu,
+                                              const Tile<T>& tRho, const Tile<T>& tUx,
+                                              const Tile<T>& tUy, T p, T m1, T m7, T m8, T dpx,
+                                              T dpy, int x, int y, const KParams<T>& P, T& Fx,
+                                              T& Fy, T& rho, T& nu) {
+  const T phi = tP(x, y);
+  rho = density<T>(phi, P.rho1, P.rho2);
+  nu = kin_visc<T>(phi, rho, P.mu1, P.mu2);
+  T dmx, dmy;
+  iso_grad<T>(tMu, x, y, dmx, dmy);
+  const T Jx = P.cJ * dmx, Jy = P.cJ * dmy;
+  const T dxyy = iso_grad_x<T>(ProdYY<T>{tPy}, x, y);
+  T dxxy, dyxy;
+  iso_grad<T>(ProdXY<T>{tPx, tPy}, x, y, dxxy, dyxy);
+  const T dyxx = iso_grad_y<T>(ProdXX<T>{tPx}, x, y);
+  const T Fsx = P.kappa * (dxyy - dyxy);
+  const T Fsy = P.kappa * (dyxx - dxxy);
+  T grx, gry, duxx, duxy, duyx, duyy;
+  iso_grad<T>(tRho, x, y, grx, gry);
+  iso_grad<T>(tUx, x, y, duxx, duxy);
+  iso_grad<T>(tUy, x, y, duyx, duyy);
+  const T Fpx = (-p) * grx, Fpy = (-p) * gry;
+  const T Fmx = Jx * duxx + Jy * duxy;
+  const T Fmy = Jx * duyx + Jy * duyy;
+  const T Fgx = (rho - P.rho_ref) * P.gx;
+  const T Fgy = (rho - P.rho_ref) * P.gy;
+  const T Frx = ((Fpx + Fsx) + Fmx) + Fgx, Fry = ((Fpy + Fsy) + Fmy) + Fgy;
+  const T brx = (P.opt & 2) ? qdiv(Frx - dpx, rho) : qdiv(Frx, rho) - dpx;
+  const T bry = (P.opt & 2) ? qdiv(Fry - dpy, rho) : qdiv(Fry, rho) - dpy;
+  const T s7 = qdiv(T(1), nu * T(3) + T(0.5));
+  T Sxx, Sxy, Syy;
+  strain_moments<T>(m1, m7, m8, p, tUx(x, y), tUy(x, y), brx, bry, P.s_g[1], s7, P.p_ref, Sxx,
+                    Sxy, Syy);
+  const T Fnx = nu * (Sxx * grx + Sxy * gry);
+  const T Fny = nu * (Sxy * grx + Syy * gry);
+  Fx = (((Fpx + Fsx) + Fnx) + Fmx) + Fgx;
+  Fy = (((Fpy + Fsy) + Fny) + Fmy) + Fgy;
+}
+
 // ------------------------------------------- a3: velocity fixed-point sweeps
 // u^{k+1} = j + F(u^k) / (2 rho)   (Eq:u), KS consecutive sweeps in one launch:
 // sweep k is evaluated on the tile grown by KS-1-k nodes, so the next sweep
 // finds its halo in LDS.  Every sweep computes exactly what a one-sweep launch
 // computes at the same node.
-template <typename T, int KS, int TX, int TY, int NT>
+template <typename T, int KS, int TX, int TY, int NT, bool SM = false>
 __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                              const T* __restrict__ praw, const T* __restrict__ jx,
                                              const T* __restrict__ jy, const T* __restrict__ uxi,
                                              const T* __restrict__ uyi, T* __restrict__ uxo,
-                                             T* __restrict__ uyo) {
+                                             T* __restrict__ uyo, const T* __restrict__ m1 = nullptr,
+                                             const T* __restrict__ m7 = nullptr,
+                                             const T* __restrict__ m8 = nullptr) {
   constexpr int HP = KS + 1;                      // phi halo
   constexpr int WP = TX + 2 * HP, HPH = TY + 2 * HP;
   constexpr int WD = TX + 2 * KS, HD = TY + 2 * KS;  // derived fields and u^0
@@ -437,12 +490,14 @@ __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* 
   __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
   constexpr int NB = KS > 1 ? 2 : 1;               // the last sweep writes to HBM
   __shared__ T sU[NB][2][WD * HD];                // ping-pong velocity iterates
+  __shared__ T sPr[SM ? WD * HD : 1];              // p, for grad p (moment strain rate)
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
   load_window<T, T, NT, WP, HPH>(sP, phi, x0 - HP, y0 - HP, P, false);
   load_window<T, T, NT, WD, HD>(sU[0][0], uxi, x0 - KS, y0 - KS, P, true);
   load_window<T, T, NT, WD, HD>(sU[0][1], uyi, x0 - KS, y0 - KS, P, true);
+  if constexpr (SM) load_window<T, T, NT, WD, HD>(sPr, praw, x0 - KS, y0 - KS, P, false);
   __syncthreads();
   const Tile<T> tP{sP, WP, HP};
   for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
@@ -473,9 +528,18 @@ __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* 
       const int x = map_idx(gxn, P.nx, P.wx, flip);
       const int y = map_idx(gyn, P.ny, P.wy, flip);
       const long long id = (long long)y * P.nx + x;
-      T Fx, Fy, rho, nu, a, b, c, d;
-      node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, praw[id], lx, ly, P, Fx, Fy, rho, nu, a, b,
-                    c, d);
+      T Fx, Fy, rho, nu;
+      if constexpr (SM) {
+        const Tile<T> tPr{sPr, WD, KS};
+        T dpx, dpy;
+        iso_grad<T>(tPr, lx, ly, dpx, dpy);
+        node_force_sm<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, praw[id], m1[id], m7[id], m8[id], dpx,
+                         dpy, lx, ly, P, Fx, Fy, rho, nu);
+      } else {
+        T a, b, c, d;
+        node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, praw[id], lx, ly, P, Fx, Fy, rho, nu, a,
+                      b, c, d);
+      }
       const T vx = jx[id] + qdiv(Fx, T(2) * rho);
       const T vy = jy[id] + qdiv(Fy, T(2) * rho);
       if (g == 0) {
@@ -525,13 +589,15 @@ __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* 
 // covers the ring of nodes around the tile, which the second sweep's stencils
 // read.  With u1x, u1y given, the first sweep's iterate is written there too
 // (the adjoint keeps every iterate).
-template <typename T, int TX, int TY, int NT>
+template <typename T, int TX, int TY, int NT, bool SM = false>
 __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                               const T* __restrict__ praw, const T* __restrict__ jx,
                                               const T* __restrict__ jy, const T* __restrict__ uxi,
                                               const T* __restrict__ uyi, T* __restrict__ uxo,
                                               T* __restrict__ uyo, T* __restrict__ u1x,
-                                              T* __restrict__ u1y) {
+                                              T* __restrict__ u1y, const T* __restrict__ m1 = nullptr,
+                                              const T* __restrict__ m7 = nullptr,
+                                              const T* __restrict__ m8 = nullptr) {
   static_assert((TX * TY) % NT == 0, "whole tile rows per thread group");
   constexpr int WP = TX + 6, HPH = TY + 6;   // phi, halo 3
   constexpr int WD = TX + 4, HD = TY + 4;    // derived fields and u^0, halo 2
@@ -541,12 +607,14 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
   __shared__ T sP[WP * HPH];
   __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
   __shared__ T sU0x[WD * HD], sU0y[WD * HD], sU1x[W1 * H1], sU1y[W1 * H1];
+  __shared__ T sPr[SM ? WD * HD : 1];        // p, for grad p (moment strain rate)
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
   load_window<T, T, NT, WP, HPH>(sP, phi, x0 - 3, y0 - 3, P, false);
   load_window<T, T, NT, WD, HD>(sU0x, uxi, x0 - 2, y0 - 2, P, true);
   load_window<T, T, NT, WD, HD>(sU0y, uyi, x0 - 2, y0 - 2, P, true);
+  if constexpr (SM) load_window<T, T, NT, WD, HD>(sPr, praw, x0 - 2, y0 - 2, P, false);
   __syncthreads();
   const Tile<T> tP{sP, WP, 3};
   for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
@@ -579,6 +647,7 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
   // products, bitwise the divisions they replace
   struct Parts {
     T Fx, Fy, Jx, Jy, gx, gy, nu, rho, jx, jy, ir2;
+    T p, dpx, dpy, m1, m7, m8, s7;   // moment strain rate only
   };
   auto parts = [&](int lx, int ly) {
     const int id = node_id(lx, ly);
@@ -606,6 +675,15 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     q.Fy = (-p) * q.gy + P.kappa * (dyxx - dxxy);
     q.Jx = P.cJ * dmx;
     q.Jy = P.cJ * dmy;
+    if constexpr (SM) {
+      const Tile<T> tPr{sPr, WD, 2};
+      q.p = p;
+      iso_grad<T>(tPr, lx, ly, q.dpx, q.dpy);
+      q.m1 = m1[id];
+      q.m7 = m7[id];
+      q.m8 = m8[id];
+      q.s7 = qdiv(T(1), q.nu * T(3) + T(0.5));
+    }
     return q;
   };
   auto sweep = [&](const Parts& q, const Tile<T>& tUx, const Tile<T>& tUy, int lx, int ly,
@@ -613,11 +691,31 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     T duxx, duxy, duyx, duyy;
     iso_grad<T>(tUx, lx, ly, duxx, duxy);
     iso_grad<T>(tUy, lx, ly, duyx, duyy);
-    const T Sxx = duxx + duxx, Sxy = duyx + duxy, Syy = duyy + duyy;
-    const T Fx = ((q.Fx + q.nu * (Sxx * q.gx + Sxy * q.gy)) + (q.Jx * duxx + q.Jy * duxy)) +
-                 (q.rho - P.rho_ref) * P.gx;
-    const T Fy = ((q.Fy + q.nu * (Sxy * q.gx + Syy * q.gy)) + (q.Jx * duyx + q.Jy * duyy)) +
-                 (q.rho - P.rho_ref) * P.gy;
+    const T Fmx = q.Jx * duxx + q.Jy * duxy, Fmy = q.Jx * duyx + q.Jy * duyy;
+    const T Fgx = (q.rho - P.rho_ref) * P.gx, Fgy = (q.rho - P.rho_ref) * P.gy;
+    T Sxx, Sxy, Syy;
+    if constexpr (SM) {
+      // b of the source corrections from the force parts other than F_nu
+      const T Frx = (q.Fx + Fmx) + Fgx, Fry = (q.Fy + Fmy) + Fgy;
+      T brx, bry;
+      if constexpr (std::is_same<T, float>::value) {
+        brx = (P.opt & 2) ? qdiv(Frx - q.dpx, q.rho) : qdiv(Frx, q.rho) - q.dpx;
+        bry = (P.opt & 2) ? qdiv(Fry - q.dpy, q.rho) : qdiv(Fry, q.rho) - q.dpy;
+      } else {
+        brx = (P.opt & 2) ? div_by(Frx - q.dpx, q.rho, T(2) * q.ir2)
+                          : div_by(Frx, q.rho, T(2) * q.ir2) - q.dpx;
+        bry = (P.opt & 2) ? div_by(Fry - q.dpy, q.rho, T(2) * q.ir2)
+                          : div_by(Fry, q.rho, T(2) * q.ir2) - q.dpy;
+      }
+      strain_moments<T>(q.m1, q.m7, q.m8, q.p, tUx(lx, ly), tUy(lx, ly), brx, bry, P.s_g[1],
+                        q.s7, P.p_ref, Sxx, Sxy, Syy);
+    } else {
+      Sxx = duxx + duxx;
+      Sxy = duyx + duxy;
+      Syy = duyy + duyy;
+    }
+    const T Fx = ((q.Fx + q.nu * (Sxx * q.gx + Sxy * q.gy)) + Fmx) + Fgx;
+    const T Fy = ((q.Fy + q.nu * (Sxy * q.gx + Syy * q.gy)) + Fmy) + Fgy;
     if constexpr (std::is_same<T, float>::value) {
       vx = q.jx + qdiv(Fx, T(2) * q.rho);
       vy = q.jy + qdiv(Fy, T(2) * q.rho);
@@ -744,7 +842,7 @@ __global__ __launch_bounds__(NT) void k_filter(KParams<T> P, int tiles_x, const 
 // ------------------------------------------------------ a5: collide + stream
 // MRT collision of f (eq:distribution_CH) and g (eq:distribution_NS) at n+1,
 // written to the streaming slots of the other parity.
-template <typename T, int PAR, bool COUPLED, bool STREAM, int TX, int TY, int NT>
+template <typename T, int PAR, bool COUPLED, bool STREAM, int TX, int TY, int NT, bool SM = false>
 __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
                                                  const T* __restrict__ phi, const T* __restrict__ pt,
                                                  const T* __restrict__ ux, const T* __restrict__ uy,
@@ -810,12 +908,23 @@ __global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __
     }
     if (COUPLED) {
       const T p = tPt(lx, ly);
-      T Fx, Fy, rho, nu, a, b, c, d;
-      node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, lx, ly, P, Fx, Fy, rho, nu, a, b, c, d);
+      T Fx, Fy, rho, nu;
       T dpx, dpy;
       iso_grad<T>(tPt, lx, ly, dpx, dpy);
+      if constexpr (SM) {
+        T m1, m7, m8;
+        moments_178<T>(g, m1, m7, m8);
+        node_force_sm<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, m1, m7, m8, dpx, dpy, lx, ly, P, Fx,
+                         Fy, rho, nu);
+      } else {
+        T a, b, c, d;
+        node_force<T>(tP, tPx, tPy, tMu, tRho, tUx, tUy, p, lx, ly, P, Fx, Fy, rho, nu, a, b, c,
+                      d);
+      }
       const T Frx = qdiv(Fx, rho), Fry = qdiv(Fy, rho);
-      const T bx = Frx - dpx, by = Fry - dpy;
+      // R8's b = F/rho - grad p, or eq:Gi as printed, (F - grad p)/rho
+      const T bx = (P.opt & 2) ? qdiv(Fx - dpx, rho) : Frx - dpx;
+      const T by = (P.opt & 2) ? qdiv(Fy - dpy, rho) : Fry - dpy;
       T geq[9], s[9];
       g_eq<T>(p - P.p_ref, u_x, u_y, geq);   // stored deviations: g^eq - 3 w p_ref
       const T tau_g = nu * T(3) + T(0.5);

@@ -206,6 +206,43 @@ __device__ __forceinline__ void mrt_collide_ms(T f[9], const T feq[9], const T m
   for (int i = 0; i < 9; ++i) f[i] = f[i] + corr[i];
 }
 
+// grad u + grad u^T from the non-equilibrium moments of the pre-collision g
+// (eq:Fmu, re-derived from App. A's first-order balances of m_1, m_7, m_8):
+// A_k = m_k - m_k^eq + G~_k / 2, div u = -(s_1/2) A_1, d_x u_x - d_y u_y =
+// -(3/2) s_7 A_7, d_x u_y + d_y u_x = -3 s_8 A_8 (s_8 = s_7).  m1 is the moment
+// of the stored populations (g_i - 3 w_i p_ref), whose m_1 is 6 p_ref larger.
+template <typename T>
+__device__ __forceinline__ void strain_moments(T m1, T m7, T m8, T p, T ux, T uy, T bx, T by,
+                                               T s1, T s7, T p_ref, T& Sxx, T& Sxy, T& Syy) {
+  const T A1 = ((m1 - T(6) * p_ref) - (T(-6) * p + T(3) * (ux * ux + uy * uy))) +
+               T(3) * (bx * ux + by * uy);
+  const T A7 = (m7 - (ux * ux - uy * uy)) + (bx * ux - by * uy);
+  const T A8 = (m8 - ux * uy) + T(0.5) * (bx * uy + by * ux);
+  const T div = (T(-0.5) * s1) * A1;
+  const T D = (T(-1.5) * s7) * A7;
+  Sxx = div + D;
+  Sxy = (T(-3) * s7) * A8;
+  Syy = div - D;
+}
+
+// m_1 = sum (3|c|^2 - 4) g, m_7 = g1 - g2 + g3 - g4, m_8 = g5 - g6 + g7 - g8 of
+// eq:D2Q9MRT, each accumulated in index order
+template <typename T>
+__device__ __forceinline__ void moments_178(const T g[9], T& m1, T& m7, T& m8) {
+  T a = T(-4) * g[0];
+  a = a - g[1];
+  a = a - g[2];
+  a = a - g[3];
+  a = a - g[4];
+  a = a + T(2) * g[5];
+  a = a + T(2) * g[6];
+  a = a + T(2) * g[7];
+  a = a + T(2) * g[8];
+  m1 = a;
+  m7 = ((g[1] - g[2]) + g[3]) - g[4];
+  m8 = ((g[5] - g[6]) + g[7]) - g[8];
+}
+
 // eq:feq_CH
 template <typename T>
 __device__ __forceinline__ void f_eq(T phi, T mu, T ux, T uy, T eta, T feq[9]) {

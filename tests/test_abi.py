@@ -44,7 +44,8 @@ def test_workspace_and_validation():
            dict(ok, eps=-1.0), dict(ok, mu1=-1.0), dict(ok, compact=True, compact_n=6),
            dict(ok, compact=True, compact_alpha=0.5), dict(ok, compact=True, compact_n=0),
            dict(ok, compact=True, nx=7681), dict(ok, p_ref=float("nan")),
-           dict(ok, p_ref=float("inf"))]
+           dict(ok, p_ref=float("inf")), dict(ok, coupled=False, strain_moments=True),
+           dict(ok, coupled=False, gi_literal=True)]
     for b in bad:
         with pytest.raises(B.LBMError, match="invalid argument"):
             B.lbm2p_workspace_bytes(B.make_params(b, 0))
@@ -132,6 +133,21 @@ def test_adjoint_workspace_and_state_checks_without_touching_the_device():
     ctx = B.lbm2p_create(cp, aligned, need, None)
     with pytest.raises(B.LBMError, match="invalid argument"):
         B.lbm2p_set_velocity(ctx, 1 << 20, 1 << 20)        # coupled: u solves Eq:u
+    B.lbm2p_destroy(ctx)
+    # options: unknown bits are invalid; the adjoint covers the default readings only
+    bad = B.make_params(ok, 0)
+    bad.options = 4
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_workspace_bytes(bad)
+    op = B.make_params(dict(ok, strain_moments=True), 0)
+    assert op.options == B.OPT_STRAIN_MOMENTS
+    need_o = B.lbm2p_workspace_bytes(op)
+    assert need_o > need                                   # m_1, m_7, m_8 planes
+    buf = ctypes.create_string_buffer(need_o + 512)
+    aligned = (ctypes.addressof(buf) + 255) // 256 * 256
+    ctx = B.lbm2p_create(op, aligned, need_o, None)
+    with pytest.raises(B.LBMError, match="invalid argument"):
+        B.lbm2p_record(ctx, 4, 2, aligned, need_o)
     B.lbm2p_destroy(ctx)
 
 

@@ -112,6 +112,47 @@ def test_original_ch_and_filter_variants():
 
 
 @pytest.mark.parametrize("kw", [
+    dict(strain_moments=True),
+    dict(strain_moments=True, K=1, wall_y=True),
+    dict(strain_moments=True, K=3, wall_x=True, wall_y=True, gy=-1e-5),
+    dict(gi_literal=True, rho2=0.1, mu2=1e-3),
+    dict(gi_literal=True, strain_moments=True, wall_y=True, K=2, rho2=0.1, mu2=1e-3),
+])
+def test_options_strain_moments_and_literal_gi(kw):
+    """The moment-based strain rate of F_nu (eq:Fmu) and the literal eq:Gi source
+    against the oracle's options, every field at 1e-12 after 1, 5 and 20 steps
+    (K = 1 and 3 exercise the one-sweep kernel, K = 2 and 3 the two-sweep one).
+    The literal eq:Gi runs at density ratio 10: at 1000 it diverges within 20
+    steps, in the oracle and the library alike (the next test)."""
+    wl = droplet_case(72, 56, seed=21, **kw)
+    st, prm = oracle_init(wl)
+    sim = gpu_sim(wl)
+    done = 0
+    for n in (1, 5, 20):
+        st = oracle.run(st, prm, n - done)
+        sim.step(n - done)
+        done = n
+        _compare_state(sim, st, label=f"{kw} step {n}")
+
+
+def test_literal_gi_diverges_at_density_ratio_1000():
+    """eq:Gi as printed, u (F - grad p)/rho, on the 1000:1 droplet of the parity
+    cases: the same first steps as the oracle (bitwise), then a blow-up within 20
+    steps on both sides (1/rho2 = 1000 multiplies the pressure gradient in the
+    second-order source), where the default reading b = F/rho - grad p runs on."""
+    wl = droplet_case(72, 56, seed=21, gi_literal=True)
+    st, prm = oracle_init(wl)
+    sim = gpu_sim(wl)
+    st = oracle.run(st, prm, 5)
+    sim.step(5)
+    _compare_state(sim, st, label="literal eq:Gi step 5")
+    st = oracle.run(st, prm, 15)
+    sim.step(15)
+    f, g, u = sim.get_state()
+    assert not bool(torch.isfinite(st.gs).all()) and not bool(torch.isfinite(g).all())
+
+
+@pytest.mark.parametrize("kw", [
     dict(compact=True, compact_n=5, compact_alpha=0.45),
     dict(compact=True, compact_n=2, compact_alpha=0.3, wall_y=True),
     dict(compact=True, compact_n=3, compact_alpha=0.49, wall_x=True, wall_y=True),

@@ -356,6 +356,7 @@ KParams<T> kparams(const lbm2p_ctx* c) {
   k.eps2 = T(c->eps2);
   k.W = T(p.W);
   k.invW = T(1.0 / p.W);
+  k.twoInvW = T(2.0 / p.W);
   k.cJ = T(c->cJ);
   k.rho1 = T(p.rho1);
   k.rho2 = T(p.rho2);

@@ -62,6 +62,7 @@ struct KParams {
   T rho1, rho2, mu1, mu2, gx, gy, rho_ref;
   T p_ref;                      // g is stored as g_i - 3 w_i p_ref
   T invW;                       // 1 / W rounded once (host)
+  T twoInvW;                    // 2 / W rounded once (host)
   T fa;                         // filter intensity
   T fd[6];                      // filter coefficients d_0..d_N
   int fn;                       // N = half width of the explicit filter
@@ -317,16 +318,25 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
     const T Mx = d4<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
     const T My = d4<T>(tM(lx, ly - 2), tM(lx, ly - 1), tM(lx, ly + 1), tM(lx, ly + 2));
     const T ph = tP(lx, ly);
-    const T mag = sqrt((Gx * Gx + Gy * Gy) + P.eps2);
-    const T nx = qdiv(Gx, mag), ny = qdiv(Gy, mag);
-    T cW;
-    if constexpr (std::is_same<T, float>::value) cW = qdiv(T(2) * (T(1) - ph * ph), P.W);
-    else cW = div_by(T(2) * (T(1) - ph * ph), P.W, P.invW);
-    const T Jpx = (mag - cW) * nx, Jpy = (mag - cW) * ny;
-    const T s = Mx * nx + My * ny;
-    const T qx = (P.negM * s) * nx, qy = (P.negM * s) * ny;
-    sJx[idx] = P.lam * Jpx + qx;
-    sJy[idx] = P.lam * Jpy + qy;
+    if constexpr (std::is_same<T, float>::value) {
+      // FP32: J_d = lambda J_phi + q = [lambda (|G| - c_W) - M (grad mu . G)/|G|] G/|G|,
+      // one reciprocal of |G|_eps and the hardware square root
+      const T mag = __builtin_amdgcn_sqrtf((Gx * Gx + Gy * Gy) + P.eps2);
+      const T r = __builtin_amdgcn_rcpf(mag);
+      const T cW = (T(1) - ph * ph) * P.twoInvW;
+      const T coef = (P.lam * (mag - cW) + (P.negM * (Mx * Gx + My * Gy)) * r) * r;
+      sJx[idx] = coef * Gx;
+      sJy[idx] = coef * Gy;
+    } else {
+      const T mag = sqrt((Gx * Gx + Gy * Gy) + P.eps2);
+      const T nx = qdiv(Gx, mag), ny = qdiv(Gy, mag);
+      const T cW = div_by(T(2) * (T(1) - ph * ph), P.W, P.invW);
+      const T Jpx = (mag - cW) * nx, Jpy = (mag - cW) * ny;
+      const T s = Mx * nx + My * ny;
+      const T qx = (P.negM * s) * nx, qy = (P.negM * s) * ny;
+      sJx[idx] = P.lam * Jpx + qx;
+      sJy[idx] = P.lam * Jpy + qy;
+    }
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
@@ -843,7 +853,7 @@ __global__ __launch_bounds__(NT) void k_filter(KParams<T> P, int tiles_x, const 
 // MRT collision of f (eq:distribution_CH) and g (eq:distribution_NS) at n+1,
 // written to the streaming slots of the other parity.
 template <typename T, int PAR, bool COUPLED, bool STREAM, int TX, int TY, int NT, bool SM = false>
-__global__ __launch_bounds__(NT) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
+__global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1) void k_collide(KParams<T> P, int tiles_x, T* __restrict__ Af, T* __restrict__ Ag,
                                                  const T* __restrict__ phi, const T* __restrict__ pt,
                                                  const T* __restrict__ ux, const T* __restrict__ uy,
                                                  const T* __restrict__ uox,

@@ -362,11 +362,21 @@ __device__ __forceinline__ T iso_lap(const A& P, int x, int y) {
   return acc * T(3);
 }
 
-// eq:chemical: mu = 4 beta (phi^3 - phi) - kappa lap(phi)
+// eq:chemical: mu = 4 beta (phi^3 - phi) - kappa lap(phi).  FP32 takes the
+// Laplacian as (2/3) sum_axes + (1/6) sum_diagonals - (10/3) P(0), the same
+// stencil in 9 operations instead of 16 (its bulk cancellation error, ~1e-7 of
+// phi, enters mu times kappa)
 template <typename T, typename A>
 __device__ __forceinline__ T chem_pot(const A& P, int x, int y, T c4b, T kappa) {
   const T p0 = P(x, y);
-  return c4b * ((p0 * p0) * p0 - p0) - kappa * iso_lap<T>(P, x, y);
+  if constexpr (std::is_same<T, float>::value) {
+    const T sa = (P(x + 1, y) + P(x - 1, y)) + (P(x, y + 1) + P(x, y - 1));
+    const T sd = (P(x + 1, y + 1) + P(x - 1, y - 1)) + (P(x - 1, y + 1) + P(x + 1, y - 1));
+    const T lap = T(2.0 / 3.0) * sa + (T(1.0 / 6.0) * sd - T(10.0 / 3.0) * p0);
+    return c4b * ((p0 * p0) * p0 - p0) - kappa * lap;
+  } else {
+    return c4b * ((p0 * p0) * p0 - p0) - kappa * iso_lap<T>(P, x, y);
+  }
 }
 
 // eq:fourOrder_FDM: [P(-2) - 8 P(-1) + 8 P(+1) - P(+2)] / 12

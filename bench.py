@@ -264,10 +264,18 @@ def cpu_baseline(wl, side, steps):
     for _ in range(steps):
         st = oracle.step_once(st, prm)
     dt = time.perf_counter() - t0
+    # the model name (some hosts report only "AMD EPYC") with family / model /
+    # stepping, which name the core generation where the name does not
     cpu = ""
     try:
+        info = {}
         with open("/proc/cpuinfo") as fh:
-            cpu = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), "")
+            for line in fh:
+                k, _, v = line.partition(":")
+                info.setdefault(k.strip(), v.strip())
+        cpu = "%s (family %s, model %s, stepping %s; %d logical CPUs)" % (
+            info.get("model name", "?"), info.get("cpu family", "?"), info.get("model", "?"),
+            info.get("stepping", "?"), os.cpu_count() or 0)
     except OSError:
         pass
     return dict(value=side * side * steps / dt / 1e6, unit="MLUPS",

@@ -394,12 +394,12 @@ struct ProfScope {
   lbm2p_ctx* c;
   bool on;
   ProfScope(lbm2p_ctx* c_, int pass) : c(c_), on(c_->prof_pass == pass && c_->prof_n < c_->ev0.size()) {
-    if (on) hipEventRecord(c->ev0[c->prof_n], c->stream);
+    // a failed record leaves the launch untimed (lbm2p_profile_read counts it out)
+    if (on) on = hipEventRecord(c->ev0[c->prof_n], c->stream) == hipSuccess;
   }
   ~ProfScope() {
     if (on) {
-      hipEventRecord(c->ev1[c->prof_n], c->stream);
-      c->prof_n++;
+      if (hipEventRecord(c->ev1[c->prof_n], c->stream) == hipSuccess) c->prof_n++;
     }
   }
 };

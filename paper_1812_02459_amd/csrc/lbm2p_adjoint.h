@@ -402,7 +402,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(
   __syncthreads();
   const Tile<T> tP{sP, W2, 2};
   if (COUPLED) {
-    derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
+    derived_halo1<T, NT, W1, H1>(tP, sPx, sPy, sMu, sRho, P);
   } else {
     for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
       const int ly = idx / W1 - 1, lx = idx % W1 - 1;
@@ -644,7 +644,7 @@ __global__ __launch_bounds__(NT) void k_adj_vel(KParams<T> P, AdjConst C, int ti
   load_window<T, T, NT, W1, H1>(sUy, uky, x0 - 1, y0 - 1, P, true);
   __syncthreads();
   const Tile<T> tP{sP, W2, 2};
-  derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
+  derived_halo1<T, NT, W1, H1>(tP, sPx, sPy, sMu, sRho, P);
   __syncthreads();
   const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
       tUx{sUx, W1, 1}, tUy{sUy, W1, 1};

@@ -106,45 +106,97 @@ __device__ __forceinline__ void tile_of(int tiles_x, int& tx, int& ty) {
   tx = t - ty * tiles_x;
 }
 
-// Load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS.  Each
-// thread first issues all of its global loads (independent, so their latencies
-// overlap), then writes them to LDS.  A window inside the lattice (most tiles)
-// takes plain row addresses; only windows that cross an edge map each index
-// through the wrap or mirror.  Node indices fit in 32 bits (checked at context
-// creation).
+// Visit every element (lx, ly), 0 <= lx < W, 0 <= ly < H, of a tile-local
+// window: columns in 64-wide chunks with lane = column (wave w of the
+// workgroup takes rows w, w + NT/64, ...), the last W % 64 columns spread over
+// all threads.  Within a chunk a thread's elements are whole rows apart, so
+// every LDS address is one per-thread base plus a compile-time offset and no
+// element pays an integer division; a wave reads 64 consecutive elements.
+template <int W, int H, int NT, typename F>
+__device__ __forceinline__ void for_window(F&& fn) {
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  constexpr int NW = NT / 64, NC = W / 64, R = W % 64;
+  constexpr int KR = (H + NW - 1) / NW;
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+#pragma unroll
+    for (int k = 0; k < KR; ++k) {
+      const int r = wv + k * NW;
+      if ((k + 1) * NW <= H || r < H) fn(c * 64 + lane, r);
+    }
+  }
+  if constexpr (R > 0) {
+    constexpr int KT = (R * H + NT - 1) / NT;
+#pragma unroll
+    for (int k = 0; k < KT; ++k) {
+      const int j = (int)threadIdx.x + k * NT;
+      if ((k + 1) * NT <= R * H || j < R * H) fn(NC * 64 + j % R, j / R);
+    }
+  }
+}
+
+// Load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS, in
+// for_window's element order.  Each thread first issues all of its global
+// loads (independent, so their latencies overlap), then writes them to LDS.
+// A thread's slots beyond the window's last row load a node of that row
+// instead (no branch around a load: a conditional load would make the
+// compiler wait for the loads before it) and are not stored.  A window inside
+// the lattice (most tiles) takes plain row addresses; only windows that cross
+// an edge map each index through the wrap or mirror.  Node indices fit in 32
+// bits (checked at context creation).
 template <typename T, typename S, int NT, int RW, int RH>
 __device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, int gx0, int gy0,
                                             const KParams<T>& P, bool odd) {
-  constexpr int N = RW * RH, IT = (N + NT - 1) / NT;
-  T v[IT];
+  static_assert(NT % 64 == 0, "whole wavefronts");
+  constexpr int NW = NT / 64, NC = RW / 64, R = RW % 64, RR = R > 0 ? R : 1;
+  constexpr int KR = (RH + NW - 1) / NW, KT = R > 0 ? (R * RH + NT - 1) / NT : 0;
+  constexpr int NV = NC * KR + KT;
+  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
+  // slot n (compile-time after unrolling) -> element (lx, ly), in the window or not
+  auto coords = [&](int n, int& lx, int& ly, bool& in) {
+    if (n < NC * KR) {
+      lx = (n / KR) * 64 + lane;
+      ly = wv + (n % KR) * NW;
+      in = ((n % KR) + 1) * NW <= RH || ly < RH;
+      ly = in ? ly : RH - 1;
+    } else {
+      int j = (int)threadIdx.x + (n - NC * KR) * NT;
+      in = (n - NC * KR + 1) * NT <= R * RH || j < R * RH;
+      j = in ? j : R * RH - 1;
+      lx = NC * 64 + j % RR;
+      ly = j / RR;
+    }
+  };
+  T v[NV];
   if (gx0 >= 0 && gx0 + RW <= P.nx && gy0 >= 0 && gy0 + RH <= P.ny) {
     const S* __restrict__ base = src + (gy0 * P.nx + gx0);
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int idx = (int)threadIdx.x + k * NT;
-      if (idx < N) {
-        const int ly = idx / RW, lx = idx - ly * RW;
-        v[k] = T(base[ly * P.nx + lx]);
-      }
+    for (int n = 0; n < NV; ++n) {
+      int lx, ly;
+      bool in;
+      coords(n, lx, ly, in);
+      v[n] = T(base[ly * P.nx + lx]);
     }
   } else {
 #pragma unroll
-    for (int k = 0; k < IT; ++k) {
-      const int idx = (int)threadIdx.x + k * NT;
-      if (idx < N) {
-        const int ly = idx / RW, lx = idx - ly * RW;
-        int flip = 0;
-        const int x = map_idx(gx0 + lx, P.nx, P.wx, flip);
-        const int y = map_idx(gy0 + ly, P.ny, P.wy, flip);
-        const T w = T(src[y * P.nx + x]);
-        v[k] = (odd && flip) ? -w : w;
-      }
+    for (int n = 0; n < NV; ++n) {
+      int lx, ly;
+      bool in;
+      coords(n, lx, ly, in);
+      int flip = 0;
+      const int x = map_idx(gx0 + lx, P.nx, P.wx, flip);
+      const int y = map_idx(gy0 + ly, P.ny, P.wy, flip);
+      const T w = T(src[y * P.nx + x]);
+      v[n] = (odd && flip) ? -w : w;
     }
   }
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int idx = (int)threadIdx.x + k * NT;
-    if (idx < N) dst[idx] = v[k];
+  for (int n = 0; n < NV; ++n) {
+    int lx, ly;
+    bool in;
+    coords(n, lx, ly, in);
+    if (in) dst[ly * RW + lx] = v[n];
   }
 }
 
@@ -306,13 +358,12 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
   load_window<T, T, NT, W5, H5>(sP, in, x0 - 5, y0 - 5, P, false);
   __syncthreads();
   const Tile<T> tP{sP, W5, 5}, tM{sM, W4, 4}, tJx{sJx, W2, 2}, tJy{sJy, W2, 2};
-  for (int idx = threadIdx.x; idx < W4 * H4; idx += NT) {
-    const int ly = idx / W4 - 4, lx = idx % W4 - 4;
-    sM[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
-  }
+  for_window<W4, H4, NT>([&](int ix, int iy) {
+    sM[iy * W4 + ix] = chem_pot<T>(tP, ix - 4, iy - 4, P.c4b, P.kappa);
+  });
   __syncthreads();
-  for (int idx = threadIdx.x; idx < W2 * H2; idx += NT) {
-    const int ly = idx / W2 - 2, lx = idx % W2 - 2;
+  for_window<W2, H2, NT>([&](int ix, int iy) {
+    const int lx = ix - 2, ly = iy - 2, idx = iy * W2 + ix;
     const T Gx = d4<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
     const T Gy = d4<T>(tP(lx, ly - 2), tP(lx, ly - 1), tP(lx, ly + 1), tP(lx, ly + 2));
     const T Mx = d4<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
@@ -337,12 +388,11 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
       sJx[idx] = P.lam * Jpx + qx;
       sJy[idx] = P.lam * Jpy + qy;
     }
-  }
+  });
   __syncthreads();
-  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
-    const int ly = idx / TX, lx = idx % TX;
+  for_window<TX, TY, NT>([&](int lx, int ly) {
     const int x = x0 + lx, y = y0 + ly;
-    if (x >= P.nx || y >= P.ny) continue;
+    if (x >= P.nx || y >= P.ny) return;
     const T L = d4<T>(tJx(lx - 2, ly), tJx(lx - 1, ly), tJx(lx + 1, ly), tJx(lx + 2, ly)) +
                 d4<T>(tJy(lx, ly - 2), tJy(lx, ly - 1), tJy(lx, ly + 1), tJy(lx, ly + 2));
     const long long id = (long long)y * P.nx + x;
@@ -363,24 +413,24 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
       r = divk<3>(phibar[id]) + divk<3>(T(2) * (pin + L));
     }
     out[id] = r;
-  }
+  });
 }
 
 // ---------------------------------------------------------- forces (a3, a5)
 // Derived fields on halo 1 shared by the velocity iteration and the collision:
 // grad phi (isotropic), mu_phi (eq:chemical), rho(clamp phi) (eq:rho).
-template <typename T, int NT>
+template <typename T, int NT, int W1, int H1>
 __device__ __forceinline__ void derived_halo1(const Tile<T>& tP, T* sPx, T* sPy, T* sMu, T* sRho,
-                                              int W1, int H1, const KParams<T>& P) {
-  for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+                                              const KParams<T>& P) {
+  for_window<W1, H1, NT>([&](int ix, int iy) {
+    const int lx = ix - 1, ly = iy - 1, idx = iy * W1 + ix;
     T gx, gy;
     iso_grad<T>(tP, lx, ly, gx, gy);
     sPx[idx] = gx;
     sPy[idx] = gy;
     sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
     sRho[idx] = density<T>(tP(lx, ly), P.rho1, P.rho2);
-  }
+  });
 }
 
 // products of grad phi for the stress-form surface force at a neighbour
@@ -510,15 +560,15 @@ __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* 
   if constexpr (SM) load_window<T, T, NT, WD, HD>(sPr, praw, x0 - KS, y0 - KS, P, false);
   __syncthreads();
   const Tile<T> tP{sP, WP, HP};
-  for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
-    const int ly = idx / WD - KS, lx = idx % WD - KS;
+  for_window<WD, HD, NT>([&](int ix, int iy) {
+    const int lx = ix - KS, ly = iy - KS, idx = iy * WD + ix;
     T gx, gy;
     iso_grad<T>(tP, lx, ly, gx, gy);
     sPx[idx] = gx;
     sPy[idx] = gy;
     sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
     sRho[idx] = density<T>(tP(lx, ly), P.rho1, P.rho2);
-  }
+  });
   __syncthreads();
   const Tile<T> tPx{sPx, WD, KS}, tPy{sPy, WD, KS}, tMu{sMu, WD, KS}, tRho{sRho, WD, KS};
 #pragma unroll
@@ -590,15 +640,21 @@ __global__ __launch_bounds__(NT) void k_vel(KParams<T> P, int tiles_x, const T* 
   }
 }
 
-// Two velocity sweeps in one launch.  phi and p are fixed
-// during the sweeps, so F_p + F_s, J = c_J grad mu, grad rho, nu and rho are the
-// same in both: on the tile's own nodes they are evaluated once and kept in
-// registers (each thread owns TX*TY/NT nodes in both sweeps), and the second
-// sweep re-evaluates only the u-dependent F_nu and F_m (F summed in the order
-// (((F_p + F_s) + F_nu) + F_m) + F_g as in node_force).  The first sweep also
-// covers the ring of nodes around the tile, which the second sweep's stencils
-// read.  With u1x, u1y given, the first sweep's iterate is written there too
-// (the adjoint keeps every iterate).
+// Two velocity sweeps in one launch.  phi and p are fixed during the sweeps,
+// so F_p + F_s, J = c_J grad mu, grad rho, nu and rho are the same in both: on
+// the tile's own nodes they are evaluated once and kept in registers (each
+// thread owns TX*TY/NT nodes in both sweeps), and the second sweep
+// re-evaluates only the u-dependent F_nu and F_m.  The first sweep also covers
+// the ring of nodes around the tile, which the second sweep's stencils read;
+// its results wait in registers until every thread has read u^0, then
+// overwrite u^0 in LDS.  grad phi enters only through the products of the
+// stress-form surface force, so LDS holds those products (each formed once
+// per node, as the force's stencils would form it at every neighbour).
+// FP64 sums F in the order (((F_p + F_s) + F_nu) + F_m) + F_g of node_force.
+// FP32 without the moment strain rate writes a sweep as the affine map
+// u^{k+1} = b + A grad u^k it is (F_nu and F_m are linear in grad u), with b
+// and the six entries of A formed once per node.  With u1x, u1y given, the
+// first sweep's iterate is written there too (the adjoint keeps every iterate).
 template <typename T, int TX, int TY, int NT, bool SM = false>
 __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T* __restrict__ phi,
                                               const T* __restrict__ praw, const T* __restrict__ jx,
@@ -610,35 +666,38 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
                                               const T* __restrict__ m8 = nullptr) {
   static_assert((TX * TY) % NT == 0, "whole tile rows per thread group");
   constexpr int WP = TX + 6, HPH = TY + 6;   // phi, halo 3
-  constexpr int WD = TX + 4, HD = TY + 4;    // derived fields and u^0, halo 2
-  constexpr int W1 = TX + 2, H1 = TY + 2;    // first sweep and u^1, halo 1
+  constexpr int WD = TX + 4, HD = TY + 4;    // derived fields and u^0, then u^1, halo 2
+  constexpr int W1 = TX + 2, H1 = TY + 2;    // first sweep, halo 1
   constexpr int NI = TX * TY / NT;           // tile nodes per thread
   constexpr int NRING = 2 * W1 + 2 * TY;     // nodes of the halo-1 ring
+  constexpr int KRING = (NRING + NT - 1) / NT;
+  constexpr bool LIN = std::is_same<T, float>::value && !SM;
   __shared__ T sP[WP * HPH];
-  __shared__ T sPx[WD * HD], sPy[WD * HD], sMu[WD * HD], sRho[WD * HD];
-  __shared__ T sU0x[WD * HD], sU0y[WD * HD], sU1x[W1 * H1], sU1y[W1 * H1];
+  __shared__ T sQxx[WD * HD], sQyy[WD * HD], sQxy[WD * HD], sMu[WD * HD], sRho[WD * HD];
+  __shared__ T sUx[WD * HD], sUy[WD * HD];
   __shared__ T sPr[SM ? WD * HD : 1];        // p, for grad p (moment strain rate)
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
   load_window<T, T, NT, WP, HPH>(sP, phi, x0 - 3, y0 - 3, P, false);
-  load_window<T, T, NT, WD, HD>(sU0x, uxi, x0 - 2, y0 - 2, P, true);
-  load_window<T, T, NT, WD, HD>(sU0y, uyi, x0 - 2, y0 - 2, P, true);
+  load_window<T, T, NT, WD, HD>(sUx, uxi, x0 - 2, y0 - 2, P, true);
+  load_window<T, T, NT, WD, HD>(sUy, uyi, x0 - 2, y0 - 2, P, true);
   if constexpr (SM) load_window<T, T, NT, WD, HD>(sPr, praw, x0 - 2, y0 - 2, P, false);
   __syncthreads();
   const Tile<T> tP{sP, WP, 3};
-  for (int idx = threadIdx.x; idx < WD * HD; idx += NT) {
-    const int ly = idx / WD - 2, lx = idx % WD - 2;
+  for_window<WD, HD, NT>([&](int ix, int iy) {
+    const int lx = ix - 2, ly = iy - 2, idx = iy * WD + ix;
     T gx, gy;
     iso_grad<T>(tP, lx, ly, gx, gy);
-    sPx[idx] = gx;
-    sPy[idx] = gy;
+    sQxx[idx] = gx * gx;
+    sQyy[idx] = gy * gy;
+    sQxy[idx] = gx * gy;
     sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
     sRho[idx] = density<T>(tP(lx, ly), P.rho1, P.rho2);
-  }
+  });
   __syncthreads();
-  const Tile<T> tPx{sPx, WD, 2}, tPy{sPy, WD, 2}, tMu{sMu, WD, 2}, tRho{sRho, WD, 2},
-      tU0x{sU0x, WD, 2}, tU0y{sU0y, WD, 2}, tU1x{sU1x, W1, 1}, tU1y{sU1y, W1, 1};
+  const Tile<T> tQxx{sQxx, WD, 2}, tQyy{sQyy, WD, 2}, tQxy{sQxy, WD, 2}, tMu{sMu, WD, 2},
+      tRho{sRho, WD, 2}, tUx{sUx, WD, 2}, tUy{sUy, WD, 2};
   // the tile grown by one lies inside the lattice: plain row addresses
   const bool inner = x0 >= 1 && x0 + W1 - 1 <= P.nx && y0 >= 1 && y0 + H1 - 1 <= P.ny;
   auto node_id = [&](int lx, int ly) {
@@ -651,7 +710,21 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     const int y = map_idx(gyn, P.ny, P.wy, flip);
     return y * P.nx + x;
   };
-  // u-independent force parts at (lx, ly), then the first sweep's u^1 there
+  // the u-independent parts of the surface force and of J at (lx, ly)
+  auto surface = [&](int lx, int ly, T& Fsx, T& Fsy, T& Jx, T& Jy, T& gx, T& gy) {
+    T dmx, dmy;
+    iso_grad<T>(tMu, lx, ly, dmx, dmy);
+    const T dxyy = iso_grad_x<T>(tQyy, lx, ly);
+    T dxxy, dyxy;
+    iso_grad<T>(tQxy, lx, ly, dxxy, dyxy);
+    const T dyxx = iso_grad_y<T>(tQxx, lx, ly);
+    iso_grad<T>(tRho, lx, ly, gx, gy);
+    Fsx = P.kappa * (dxyy - dyxy);
+    Fsy = P.kappa * (dyxx - dxxy);
+    Jx = P.cJ * dmx;
+    Jy = P.cJ * dmy;
+  };
+  // FP64 / moment strain rate: the force parts, summed in the sweep.
   // FP64: ir2 = 1/(2 rho) rounded once; the four quotients by 2 rho of the two
   // sweeps and nu = mu/rho (2 ir2 = RN(1/rho) exactly) are then FMA-corrected
   // products, bitwise the divisions they replace
@@ -659,100 +732,107 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     T Fx, Fy, Jx, Jy, gx, gy, nu, rho, jx, jy, ir2;
     T p, dpx, dpy, m1, m7, m8, s7;   // moment strain rate only
   };
+  // FP32: u^{k+1} = b + A (duxx, duxy, duyx, duyy)
+  struct Lin {
+    T bx, by, a1, a2, a3, b1, b2, b3;
+  };
+  using Node = typename std::conditional<LIN, Lin, Parts>::type;
   auto parts = [&](int lx, int ly) {
     const int id = node_id(lx, ly);
-    Parts q;
+    Node q;
     const T p = praw[id];
-    q.jx = jx[id];
-    q.jy = jy[id];
     const T ph = tP(lx, ly);
-    q.rho = density<T>(ph, P.rho1, P.rho2);
-    if constexpr (std::is_same<T, float>::value) {
-      q.nu = kin_visc<T>(ph, q.rho, P.mu1, P.mu2);
-      q.ir2 = T(0);
+    T Fsx, Fsy, Jx, Jy, gx, gy;
+    surface(lx, ly, Fsx, Fsy, Jx, Jy, gx, gy);
+    if constexpr (LIN) {
+      const T rho = density<T>(ph, P.rho1, P.rho2);
+      const T ir = __builtin_amdgcn_rcpf(rho);
+      const T nu = dyn_visc<T>(ph, P.mu1, P.mu2) * ir;
+      const T r2 = T(0.5) * ir;
+      const T Fcx = ((-p) * gx + Fsx) + (rho - P.rho_ref) * P.gx;
+      const T Fcy = ((-p) * gy + Fsy) + (rho - P.rho_ref) * P.gy;
+      const T ngx = nu * gx, ngy = nu * gy;
+      q.bx = jx[id] + Fcx * r2;
+      q.by = jy[id] + Fcy * r2;
+      q.a1 = ((ngx + ngx) + Jx) * r2;
+      q.a2 = (ngy + Jy) * r2;
+      q.a3 = ngy * r2;
+      q.b1 = ngx * r2;
+      q.b2 = (ngx + Jx) * r2;
+      q.b3 = ((ngy + ngy) + Jy) * r2;
     } else {
-      q.ir2 = T(1) / (T(2) * q.rho);
-      q.nu = div_by(dyn_visc<T>(ph, P.mu1, P.mu2), q.rho, T(2) * q.ir2);
-    }
-    T dmx, dmy;
-    iso_grad<T>(tMu, lx, ly, dmx, dmy);
-    const T dxyy = iso_grad_x<T>(ProdYY<T>{tPy}, lx, ly);
-    T dxxy, dyxy;
-    iso_grad<T>(ProdXY<T>{tPx, tPy}, lx, ly, dxxy, dyxy);
-    const T dyxx = iso_grad_y<T>(ProdXX<T>{tPx}, lx, ly);
-    iso_grad<T>(tRho, lx, ly, q.gx, q.gy);
-    q.Fx = (-p) * q.gx + P.kappa * (dxyy - dyxy);
-    q.Fy = (-p) * q.gy + P.kappa * (dyxx - dxxy);
-    q.Jx = P.cJ * dmx;
-    q.Jy = P.cJ * dmy;
-    if constexpr (SM) {
-      const Tile<T> tPr{sPr, WD, 2};
-      q.p = p;
-      iso_grad<T>(tPr, lx, ly, q.dpx, q.dpy);
-      q.m1 = m1[id];
-      q.m7 = m7[id];
-      q.m8 = m8[id];
-      q.s7 = qdiv(T(1), q.nu * T(3) + T(0.5));
+      q.jx = jx[id];
+      q.jy = jy[id];
+      q.rho = density<T>(ph, P.rho1, P.rho2);
+      if constexpr (std::is_same<T, float>::value) {
+        q.nu = kin_visc<T>(ph, q.rho, P.mu1, P.mu2);
+        q.ir2 = T(0);
+      } else {
+        q.ir2 = T(1) / (T(2) * q.rho);
+        q.nu = div_by(dyn_visc<T>(ph, P.mu1, P.mu2), q.rho, T(2) * q.ir2);
+      }
+      q.gx = gx;
+      q.gy = gy;
+      q.Fx = (-p) * gx + Fsx;
+      q.Fy = (-p) * gy + Fsy;
+      q.Jx = Jx;
+      q.Jy = Jy;
+      if constexpr (SM) {
+        const Tile<T> tPr{sPr, WD, 2};
+        q.p = p;
+        iso_grad<T>(tPr, lx, ly, q.dpx, q.dpy);
+        q.m1 = m1[id];
+        q.m7 = m7[id];
+        q.m8 = m8[id];
+        q.s7 = qdiv(T(1), q.nu * T(3) + T(0.5));
+      }
     }
     return q;
   };
-  auto sweep = [&](const Parts& q, const Tile<T>& tUx, const Tile<T>& tUy, int lx, int ly,
-                   T& vx, T& vy) {
+  auto sweep = [&](const Node& q, int lx, int ly, T& vx, T& vy) {
     T duxx, duxy, duyx, duyy;
     iso_grad<T>(tUx, lx, ly, duxx, duxy);
     iso_grad<T>(tUy, lx, ly, duyx, duyy);
-    const T Fmx = q.Jx * duxx + q.Jy * duxy, Fmy = q.Jx * duyx + q.Jy * duyy;
-    const T Fgx = (q.rho - P.rho_ref) * P.gx, Fgy = (q.rho - P.rho_ref) * P.gy;
-    T Sxx, Sxy, Syy;
-    if constexpr (SM) {
-      // b of the source corrections from the force parts other than F_nu
-      const T Frx = (q.Fx + Fmx) + Fgx, Fry = (q.Fy + Fmy) + Fgy;
-      T brx, bry;
-      if constexpr (std::is_same<T, float>::value) {
-        brx = (P.opt & 2) ? qdiv(Frx - q.dpx, q.rho) : qdiv(Frx, q.rho) - q.dpx;
-        bry = (P.opt & 2) ? qdiv(Fry - q.dpy, q.rho) : qdiv(Fry, q.rho) - q.dpy;
+    if constexpr (LIN) {
+      vx = ((q.bx + q.a1 * duxx) + q.a2 * duxy) + q.a3 * duyx;
+      vy = ((q.by + q.b1 * duxy) + q.b2 * duyx) + q.b3 * duyy;
+    } else {
+      const T Fmx = q.Jx * duxx + q.Jy * duxy, Fmy = q.Jx * duyx + q.Jy * duyy;
+      const T Fgx = (q.rho - P.rho_ref) * P.gx, Fgy = (q.rho - P.rho_ref) * P.gy;
+      T Sxx, Sxy, Syy;
+      if constexpr (SM) {
+        // b of the source corrections from the force parts other than F_nu
+        const T Frx = (q.Fx + Fmx) + Fgx, Fry = (q.Fy + Fmy) + Fgy;
+        T brx, bry;
+        if constexpr (std::is_same<T, float>::value) {
+          brx = (P.opt & 2) ? qdiv(Frx - q.dpx, q.rho) : qdiv(Frx, q.rho) - q.dpx;
+          bry = (P.opt & 2) ? qdiv(Fry - q.dpy, q.rho) : qdiv(Fry, q.rho) - q.dpy;
+        } else {
+          brx = (P.opt & 2) ? div_by(Frx - q.dpx, q.rho, T(2) * q.ir2)
+                            : div_by(Frx, q.rho, T(2) * q.ir2) - q.dpx;
+          bry = (P.opt & 2) ? div_by(Fry - q.dpy, q.rho, T(2) * q.ir2)
+                            : div_by(Fry, q.rho, T(2) * q.ir2) - q.dpy;
+        }
+        strain_moments<T>(q.m1, q.m7, q.m8, q.p, tUx(lx, ly), tUy(lx, ly), brx, bry, P.s_g[1],
+                          q.s7, P.p_ref, Sxx, Sxy, Syy);
       } else {
-        brx = (P.opt & 2) ? div_by(Frx - q.dpx, q.rho, T(2) * q.ir2)
-                          : div_by(Frx, q.rho, T(2) * q.ir2) - q.dpx;
-        bry = (P.opt & 2) ? div_by(Fry - q.dpy, q.rho, T(2) * q.ir2)
-                          : div_by(Fry, q.rho, T(2) * q.ir2) - q.dpy;
+        Sxx = duxx + duxx;
+        Sxy = duyx + duxy;
+        Syy = duyy + duyy;
       }
-      strain_moments<T>(q.m1, q.m7, q.m8, q.p, tUx(lx, ly), tUy(lx, ly), brx, bry, P.s_g[1],
-                        q.s7, P.p_ref, Sxx, Sxy, Syy);
-    } else {
-      Sxx = duxx + duxx;
-      Sxy = duyx + duxy;
-      Syy = duyy + duyy;
-    }
-    const T Fx = ((q.Fx + q.nu * (Sxx * q.gx + Sxy * q.gy)) + Fmx) + Fgx;
-    const T Fy = ((q.Fy + q.nu * (Sxy * q.gx + Syy * q.gy)) + Fmy) + Fgy;
-    if constexpr (std::is_same<T, float>::value) {
-      vx = q.jx + qdiv(Fx, T(2) * q.rho);
-      vy = q.jy + qdiv(Fy, T(2) * q.rho);
-    } else {
-      vx = q.jx + div_by(Fx, T(2) * q.rho, q.ir2);
-      vy = q.jy + div_by(Fy, T(2) * q.rho, q.ir2);
+      const T Fx = ((q.Fx + q.nu * (Sxx * q.gx + Sxy * q.gy)) + Fmx) + Fgx;
+      const T Fy = ((q.Fy + q.nu * (Sxy * q.gx + Syy * q.gy)) + Fmy) + Fgy;
+      if constexpr (std::is_same<T, float>::value) {
+        vx = q.jx + qdiv(Fx, T(2) * q.rho);
+        vy = q.jy + qdiv(Fy, T(2) * q.rho);
+      } else {
+        vx = q.jx + div_by(Fx, T(2) * q.rho, q.ir2);
+        vy = q.jy + div_by(Fy, T(2) * q.rho, q.ir2);
+      }
     }
   };
-  Parts c[NI];
-#pragma unroll
-  for (int r = 0; r < NI; ++r) {
-    const int idx = threadIdx.x + r * NT;
-    const int ly = idx / TX, lx = idx - ly * TX;
-    c[r] = parts(lx, ly);
-    T vx, vy;
-    sweep(c[r], tU0x, tU0y, lx, ly, vx, vy);
-    sU1x[(ly + 1) * W1 + lx + 1] = vx;
-    sU1y[(ly + 1) * W1 + lx + 1] = vy;
-    if (u1x != nullptr && x0 + lx < P.nx && y0 + ly < P.ny) {
-      const int id = (y0 + ly) * P.nx + x0 + lx;
-      u1x[id] = vx;
-      u1y[id] = vy;
-    }
-  }
-  // the ring: rows -1 and TY (W1 nodes each), then columns -1 and TX
-  for (int k = threadIdx.x; k < NRING; k += NT) {
-    int lx, ly;
+  auto ring_node = [&](int k, int& lx, int& ly) {
+    // rows -1 and TY (W1 nodes each), then columns -1 and TX
     if (k < 2 * W1) {
       ly = k < W1 ? -1 : TY;
       lx = (k < W1 ? k : k - W1) - 1;
@@ -761,35 +841,73 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
       ly = j >> 1;
       lx = (j & 1) ? TX : -1;
     }
-    const Parts q = parts(lx, ly);
-    T vx, vy;
-    sweep(q, tU0x, tU0y, lx, ly, vx, vy);
-    sU1x[(ly + 1) * W1 + lx + 1] = vx;
-    sU1y[(ly + 1) * W1 + lx + 1] = vy;
+  };
+  // first sweep on the tile's nodes and its ring, from u^0
+  Node c[NI];
+  T v1x[NI], v1y[NI], rvx[KRING], rvy[KRING];
+#pragma unroll
+  for (int r = 0; r < NI; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    const int ly = idx / TX, lx = idx - ly * TX;
+    c[r] = parts(lx, ly);
+    sweep(c[r], lx, ly, v1x[r], v1y[r]);
+    if (u1x != nullptr && x0 + lx < P.nx && y0 + ly < P.ny) {
+      const int id = (y0 + ly) * P.nx + x0 + lx;
+      u1x[id] = v1x[r];
+      u1y[id] = v1y[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < KRING; ++r) {
+    const int k = threadIdx.x + r * NT;
+    if (k < NRING) {
+      int lx, ly;
+      ring_node(k, lx, ly);
+      const Node q = parts(lx, ly);
+      sweep(q, lx, ly, rvx[r], rvy[r]);
+    }
+  }
+  __syncthreads();   // every read of u^0 done: u^1 replaces it on halo 1
+#pragma unroll
+  for (int r = 0; r < NI; ++r) {
+    const int idx = threadIdx.x + r * NT;
+    const int ly = idx / TX, lx = idx - ly * TX;
+    tUx.at(lx, ly) = v1x[r];
+    tUy.at(lx, ly) = v1y[r];
+  }
+#pragma unroll
+  for (int r = 0; r < KRING; ++r) {
+    const int k = threadIdx.x + r * NT;
+    if (k < NRING) {
+      int lx, ly;
+      ring_node(k, lx, ly);
+      tUx.at(lx, ly) = rvx[r];
+      tUy.at(lx, ly) = rvy[r];
+    }
   }
   __syncthreads();
   if (P.wx || P.wy) {
     // no-slip ghosts of u^1: the mirror node's value, sign flipped once per
-    // mirrored axis (as the oracle's ghost extension does)
-    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+    // mirrored axis (as the oracle's ghost extension does).  Ghost and mirror
+    // sets are disjoint, so reads and writes do not overlap
+    for_window<W1, H1, NT>([&](int ix, int iy) {
+      const int lx = ix - 1, ly = iy - 1;
       const int gxn = x0 + lx, gyn = y0 + ly;
       int mx = gxn, my = gyn, flips = 0;
       if (P.wx && gxn < 0) { mx = -1 - gxn; flips ^= 1; }
       if (P.wx && gxn >= P.nx) { mx = 2 * P.nx - 1 - gxn; flips ^= 1; }
       if (P.wy && gyn < 0) { my = -1 - gyn; flips ^= 1; }
       if (P.wy && gyn >= P.ny) { my = 2 * P.ny - 1 - gyn; flips ^= 1; }
-      if (mx == gxn && my == gyn) continue;            // not a ghost
+      if (mx == gxn && my == gyn) return;              // not a ghost
       const int lmx = mx - x0, lmy = my - y0;
       T vx = T(0), vy = T(0);                          // never read by an in-domain output
       if (lmx >= -1 && lmx < TX + 1 && lmy >= -1 && lmy < TY + 1) {
-        const int om = (lmy + 1) * W1 + (lmx + 1);
-        vx = flips ? -sU1x[om] : sU1x[om];
-        vy = flips ? -sU1y[om] : sU1y[om];
+        vx = flips ? -tUx(lmx, lmy) : tUx(lmx, lmy);
+        vy = flips ? -tUy(lmx, lmy) : tUy(lmx, lmy);
       }
-      sU1x[idx] = vx;
-      sU1y[idx] = vy;
-    }
+      tUx.at(lx, ly) = vx;
+      tUy.at(lx, ly) = vy;
+    });
     __syncthreads();
   }
   // second sweep from u^1 on the tile's own nodes
@@ -800,7 +918,7 @@ __global__ __launch_bounds__(NT) void k_vel2(KParams<T> P, int tiles_x, const T*
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) continue;
     T vx, vy;
-    sweep(c[r], tU1x, tU1y, lx, ly, vx, vy);
+    sweep(c[r], lx, ly, vx, vy);
     const int id = y * P.nx + x;
     uxo[id] = vx;
     uyo[id] = vy;
@@ -872,12 +990,11 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1) void k_c
   __syncthreads();
   const Tile<T> tP{sP, W2, 2};
   if (COUPLED) {
-    derived_halo1<T, NT>(tP, sPx, sPy, sMu, sRho, W1, H1, P);
+    derived_halo1<T, NT, W1, H1>(tP, sPx, sPy, sMu, sRho, P);
   } else {
-    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
-      sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
-    }
+    for_window<W1, H1, NT>([&](int ix, int iy) {
+      sMu[iy * W1 + ix] = chem_pot<T>(tP, ix - 1, iy - 1, P.c4b, P.kappa);
+    });
   }
   __syncthreads();
   const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},

@@ -356,7 +356,10 @@ KParams<T> kparams(const lbm2p_ctx* c) {
   k.eps2 = T(c->eps2);
   k.W = T(p.W);
   k.invW = T(1.0 / p.W);
-  k.twoInvW = T(2.0 / p.W);
+  k.lam12 = T(p.lam / 12.0);
+  k.lamW2 = T(2.0 * p.lam / p.W);
+  k.negM12 = T(-p.M / 12.0);
+  k.eps144 = T(144.0 * c->eps2);
   k.cJ = T(c->cJ);
   k.rho1 = T(p.rho1);
   k.rho2 = T(p.rho2);

@@ -32,7 +32,7 @@ namespace lbm2p {
 // collision its COLT shape (128^2 CH-only step 29 -> 20 us FP32; 200^2
 // droplet 53 -> 34 us FP32, 77 -> 49 us FP64).
 #ifndef LBM2P_F32_TILES
-#define LBM2P_F32_TILES 64, 1024, 16, 512, 32, 512, 16, 512, 128, 32, 512, 8, 512, 64
+#define LBM2P_F32_TILES 64, 1024, 32, 1024, 32, 512, 16, 512, 128, 32, 512, 8, 512, 64
 #endif
 #ifndef LBM2P_F64_TILES
 #define LBM2P_F64_TILES 16, 512, 8, 512, 16, 512, 16, 256, 64, 16, 512, 4, 256, 64
@@ -62,7 +62,7 @@ struct KParams {
   T rho1, rho2, mu1, mu2, gx, gy, rho_ref;
   T p_ref;                      // g is stored as g_i - 3 w_i p_ref
   T invW;                       // 1 / W rounded once (host)
-  T twoInvW;                    // 2 / W rounded once (host)
+  T lam12, lamW2, negM12, eps144;  // FP32 FD stage: lambda/12, 2 lambda/W, -M/12, 144 eps^2
   T fa;                         // filter intensity
   T fd[6];                      // filter coefficients d_0..d_N
   int fn;                       // N = half width of the explicit filter
@@ -134,6 +134,15 @@ __device__ __forceinline__ void for_window(F&& fn) {
       if ((k + 1) * NT <= R * H || j < R * H) fn(NC * 64 + j % R, j / R);
     }
   }
+}
+
+// Element k of one field plane (k < 2^31 / 9 nodes, so k * 8 < 2^32): the
+// uniform base plus a 32-bit byte offset, so that a load or store takes the
+// base from scalar registers and one vector register for the offset (the
+// gather's stores; elsewhere measured no faster than 64-bit addresses).
+template <typename T>
+__device__ __forceinline__ T& fld(T* base, long long k) {
+  return *(T*)((char*)base + (unsigned)k * (unsigned)sizeof(T));
 }
 
 // Load a (RW x RH) window whose (0,0) sits at node (gx0, gy0) into LDS, in
@@ -229,6 +238,22 @@ __device__ __forceinline__ void pop_st(T* p, T v) {
   if constexpr (STREAM && ((LBM2P_POP_NT >> BIT) & 1) != 0) __builtin_nontemporal_store(v, p);
   else *p = v;
 }
+// Slot addresses of the gather: the two slots direction i can use, in planes i
+// and opp(i), are addressed from plane lo(i) = min(i, opp(i)) (a uniform base)
+// by an element offset rd[i] < 3 planes.  FP32 adds it as a 32-bit byte offset
+// (3 planes of < 2^31 / 9 four-byte elements stay below 2^32), so a load takes
+// its base from scalar registers and one vector register; FP64 adds elements.
+// (The collision keeps 64-bit addresses from the distribution's base: with
+// plane bases its FP64 build runs out of scalar registers and its FP32 build,
+// though it needs fewer vector registers, measured 2 % slower.)
+__host__ __device__ constexpr int lo_of(int i) { return i < opp(i) ? i : opp(i); }
+template <int I, typename T>
+__device__ __forceinline__ T* slot_ptr(T* A, long long ps, int r) {
+  T* plane = A + lo_of(I) * ps;
+  if constexpr (sizeof(T) == 4) return (T*)((char*)plane + (unsigned)r * 4u);
+  else return plane + r;
+}
+
 // The collision's nine loads (v[i] from slot rd[i]) and stores (v[i] to slot
 // rd[opp(i)]) of one distribution, each with its direction's alignment known
 // at compile time.
@@ -242,21 +267,26 @@ __device__ __forceinline__ void col_store9(T* A, const int* rd, const T* v,
                                            std::integer_sequence<int, I...>) {
   (pop_st<4 + PAR, STREAM && (PAR == 1 || cx_of(I) == 0)>(A + rd[opp(I)], v[I]), ...);
 }
+template <int PAR, bool STREAM, typename T, int... I>
+__device__ __forceinline__ void gather_load9(const T* A, long long ps, const int* rd, T* v,
+                                             std::integer_sequence<int, I...>) {
+  ((v[I] = pop_ld<PAR, STREAM>(slot_ptr<I>(A, ps, rd[I]))), ...);
+}
 
 // ------------------------------------------------------------- populations
-// Element offsets (from a distribution's base) of the nine slots node (x, y)
-// pulls f_i from.  In both parities the node writes f*_opp(i) back to the slot
-// it pulled f_i from (parity 0: the slot of x - c_i, or its own slot i beyond a
-// wall; parity 1: its own slot i), so one set of offsets serves the pull and
-// the push of f and of g.  32-bit offsets: 9 planes < 2^31 elements (checked
-// at context creation).
-template <int PAR, typename T>
+// Element offsets (from a distribution's base, or with REL from plane lo(i)
+// of it, for slot_ptr) of the nine slots node (x, y) pulls f_i from.  In both parities the node writes f*_opp(i) back to
+// the slot it pulled f_i from (parity 0: the slot of x - c_i, or its own slot
+// i beyond a wall; parity 1: its own slot i), so one set of offsets serves the
+// pull and the push of f and of g.  32-bit offsets: 9 planes < 2^31 elements
+// (checked at context creation).
+template <int PAR, bool REL, typename T>
 __device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[9]) {
   const int ps = (int)P.ps;
   const int id = y * P.nx + x;
   if (PAR == 1) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) rd[i] = i * ps + id;
+    for (int i = 0; i < 9; ++i) rd[i] = (i - (REL ? lo_of(i) : 0)) * ps + id;
     return;
   }
   const bool lo_x = x == 0, hi_x = x == P.nx - 1, lo_y = y == 0, hi_y = y == P.ny - 1;
@@ -270,7 +300,8 @@ __device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[
     const int sr = cy == 1 ? rm : (cy == -1 ? rp : r0);
     const bool out = (P.wx && ((cx == 1 && lo_x) || (cx == -1 && hi_x))) ||
                      (P.wy && ((cy == 1 && lo_y) || (cy == -1 && hi_y)));
-    rd[i] = out ? i * ps + id : opp(i) * ps + sr + sx;
+    const int b = REL ? lo_of(i) : 0;
+    rd[i] = out ? (i - b) * ps + id : (opp(i) - b) * ps + sr + sx;
   }
 }
 
@@ -289,31 +320,31 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   if (id >= n) return;
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
   int rd[9];
-  slots<PAR>(P, x, y, rd);
+  slots<PAR, true>(P, x, y, rd);
   if constexpr (std::is_same<T, float>::value) {
     // FP32: the eight moving populations (|f_i| << 1) summed first, f_0 ~ phi
     // added last, so that the sum rounds once at phi's magnitude
     T f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) f[i] = pop_ld<PAR, STREAM>(Af + rd[i]);
-    phibar[id] = f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+    gather_load9<PAR, STREAM>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
+    fld(phibar, id) = f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
   } else {
-    T s = pop_ld<PAR, STREAM>(Af + rd[0]);
+    T f[9];
+    gather_load9<PAR, STREAM>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
+    T s = f[0];
 #pragma unroll
-    for (int i = 1; i < 9; ++i) s = s + pop_ld<PAR, STREAM>(Af + rd[i]);
-    phibar[id] = s;
+    for (int i = 1; i < 9; ++i) s = s + f[i];
+    fld(phibar, id) = s;
   }
   if (!COUPLED) return;
   T g[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) g[i] = pop_ld<PAR, STREAM>(Ag + rd[i]);
+  gather_load9<PAR, STREAM>(Ag, P.ps, rd, g, std::make_integer_sequence<int, 9>{});
   T sg = g[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) sg = sg + g[i];
   // FP32: the correctly rounded sg / 3 (sg times the rounded 1/3 would scale p
   // by 1 + 3e-8 every step, a drift the collision carries forward)
-  if constexpr (std::is_same<T, float>::value) praw[id] = div3_rn(sg) + P.p_ref;
-  else praw[id] = divk<3>(sg) + P.p_ref;   // sum_i 3 w_i p_ref / 3 = p_ref
+  if constexpr (std::is_same<T, float>::value) fld(praw, id) = div3_rn(sg) + P.p_ref;
+  else fld(praw, id) = divk<3>(sg) + P.p_ref;   // sum_i 3 w_i p_ref / 3 = p_ref
   T ax = g[1];
   ax = ax - g[3];
   ax = ax + g[5];
@@ -326,16 +357,16 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   ay = ay + g[6];
   ay = ay - g[7];
   ay = ay - g[8];
-  jx[id] = ax;
-  jy[id] = ay;
+  fld(jx, id) = ax;
+  fld(jy, id) = ay;
   if (m7) {
-    m7[id] = ((g[1] - g[2]) + g[3]) - g[4];
-    m8[id] = ((g[5] - g[6]) + g[7]) - g[8];
+    fld(m7, id) = ((g[1] - g[2]) + g[3]) - g[4];
+    fld(m8, id) = ((g[5] - g[6]) + g[7]) - g[8];
   }
   if (m1) {
     T a, b, c;
     moments_178<T>(g, a, b, c);
-    m1[id] = a;
+    fld(m1, id) = a;
   }
 }
 
@@ -364,21 +395,28 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
   __syncthreads();
   for_window<W2, H2, NT>([&](int ix, int iy) {
     const int lx = ix - 2, ly = iy - 2, idx = iy * W2 + ix;
-    const T Gx = d4<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
-    const T Gy = d4<T>(tP(lx, ly - 2), tP(lx, ly - 1), tP(lx, ly + 1), tP(lx, ly + 2));
-    const T Mx = d4<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
-    const T My = d4<T>(tM(lx, ly - 2), tM(lx, ly - 1), tM(lx, ly + 1), tM(lx, ly + 2));
     const T ph = tP(lx, ly);
     if constexpr (std::is_same<T, float>::value) {
-      // FP32: J_d = lambda J_phi + q = [lambda (|G| - c_W) - M (grad mu . G)/|G|] G/|G|,
-      // one reciprocal of |G|_eps and the hardware square root
-      const T mag = __builtin_amdgcn_sqrtf((Gx * Gx + Gy * Gy) + P.eps2);
+      // FP32: J_d = lambda J_phi + q = [lambda (|G| - c_W) - M (grad mu . G)/|G|] G/|G|
+      // from the unscaled differences G' = 12 G, M' = 12 grad mu:
+      // J_d = [lambda/12 |G'|_e - lambda c_W - (M/12) (M'.G') / |G'|_e] G' / |G'|_e with
+      // |G'|_e = sqrt(|G'|^2 + 144 eps^2) = 12 |G|_eps, the 1/12 in the constants;
+      // one reciprocal and the hardware square root
+      const T Gx = d4u<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
+      const T Gy = d4u<T>(tP(lx, ly - 2), tP(lx, ly - 1), tP(lx, ly + 1), tP(lx, ly + 2));
+      const T Mx = d4u<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
+      const T My = d4u<T>(tM(lx, ly - 2), tM(lx, ly - 1), tM(lx, ly + 1), tM(lx, ly + 2));
+      const T mag = __builtin_amdgcn_sqrtf((Gx * Gx + Gy * Gy) + P.eps144);
       const T r = __builtin_amdgcn_rcpf(mag);
-      const T cW = (T(1) - ph * ph) * P.twoInvW;
-      const T coef = (P.lam * (mag - cW) + (P.negM * (Mx * Gx + My * Gy)) * r) * r;
+      const T a = P.lam12 * mag + (ph * ph - T(1)) * P.lamW2;
+      const T coef = (a + P.negM12 * ((Mx * Gx + My * Gy) * r)) * r;
       sJx[idx] = coef * Gx;
       sJy[idx] = coef * Gy;
     } else {
+      const T Gx = d4<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
+      const T Gy = d4<T>(tP(lx, ly - 2), tP(lx, ly - 1), tP(lx, ly + 1), tP(lx, ly + 2));
+      const T Mx = d4<T>(tM(lx - 2, ly), tM(lx - 1, ly), tM(lx + 1, ly), tM(lx + 2, ly));
+      const T My = d4<T>(tM(lx, ly - 2), tM(lx, ly - 1), tM(lx, ly + 1), tM(lx, ly + 2));
       const T mag = sqrt((Gx * Gx + Gy * Gy) + P.eps2);
       const T nx = qdiv(Gx, mag), ny = qdiv(Gy, mag);
       const T cW = div_by(T(2) * (T(1) - ph * ph), P.W, P.invW);
@@ -393,8 +431,14 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
   for_window<TX, TY, NT>([&](int lx, int ly) {
     const int x = x0 + lx, y = y0 + ly;
     if (x >= P.nx || y >= P.ny) return;
-    const T L = d4<T>(tJx(lx - 2, ly), tJx(lx - 1, ly), tJx(lx + 1, ly), tJx(lx + 2, ly)) +
-                d4<T>(tJy(lx, ly - 2), tJy(lx, ly - 1), tJy(lx, ly + 1), tJy(lx, ly + 2));
+    // FP32: the divergence's 1/12 applied once to the sum of the unscaled differences
+    const T L =
+        std::is_same<T, float>::value
+            ? (d4u<T>(tJx(lx - 2, ly), tJx(lx - 1, ly), tJx(lx + 1, ly), tJx(lx + 2, ly)) +
+               d4u<T>(tJy(lx, ly - 2), tJy(lx, ly - 1), tJy(lx, ly + 1), tJy(lx, ly + 2))) *
+                  T(1.0 / 12.0)
+            : d4<T>(tJx(lx - 2, ly), tJx(lx - 1, ly), tJx(lx + 1, ly), tJx(lx + 2, ly)) +
+                  d4<T>(tJy(lx, ly - 2), tJy(lx, ly - 1), tJy(lx, ly + 1), tJy(lx, ly + 2));
     const long long id = (long long)y * P.nx + x;
     const T pin = tP(lx, ly);
     T r;
@@ -1012,7 +1056,7 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1) void k_c
     const T ax = (u_x - uox[id]) + (u_x * duxx + u_y * duxy);
     const T ay = (u_y - uoy[id]) + (u_x * duyx + u_y * duyy);
     int rd[9];
-    slots<PAR>(P, x, y, rd);
+    slots<PAR, false>(P, x, y, rd);
     T g[9];
     {
       T f[9], feq[9];

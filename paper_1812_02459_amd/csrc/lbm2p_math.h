@@ -402,6 +402,13 @@ __device__ __forceinline__ T d4(T m2, T m1, T p1, T p2) {
   return divk<12>(((m2 - T(8) * m1) + T(8) * p1) - p2);
 }
 
+// twelve times eq:fourOrder_FDM, [P(-2) - P(+2)] + 8 [P(+1) - P(-1)] (FP32
+// folds the 1/12 into the constants it meets)
+template <typename T>
+__device__ __forceinline__ T d4u(T m2, T m1, T p1, T p2) {
+  return (m2 - p2) + T(8) * (p1 - m1);
+}
+
 // eq:rho and eq:dynamic_vis on clamp(phi, -1, 1); NaN passes through
 template <typename T>
 __device__ __forceinline__ T clamp1(T p) {

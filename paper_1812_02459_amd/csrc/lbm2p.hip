@@ -109,7 +109,7 @@ void compact_coeffs(int N, double alpha, double* a) {
 // nodes: periodic -> cyclic matrix split as B + u v^T (Sherman-Morrison with
 // gamma = -1); wall -> end rows 1 + sgn alpha (mirror ghosts).
 void compact_table(int n, double alpha, bool cyclic, double sgn, double* cp, double* inv,
-                   double* z, double* fac, double* den, int* flat) {
+                   double* z, double* fac, double* den, int* flat, int* z0, int* z1) {
   std::vector<double> b(n, 1.0);
   double gamma = 0;
   if (cyclic) {
@@ -148,6 +148,22 @@ void compact_table(int n, double alpha, bool cyclic, double sgn, double* cp, dou
     for (int i = 0; i < n; ++i) z[i] = 0.0;
     *fac = 0;
     *den = 1;
+  }
+  // z decays from both ends: [z0, z1) holds only |z_i| <= 1e-30 max|z| (the
+  // device drops f z_i there); every larger entry of the first half lies below
+  // z0, of the second half at or above z1
+  double zmax = 0;
+  for (int i = 0; i < n; ++i) zmax = std::max(zmax, std::fabs(z[i]));
+  const double thr = 1e-30 * zmax;
+  *z0 = 0;
+  *z1 = n;
+  for (int i = 0; i < n / 2; ++i)
+    if (std::fabs(z[i]) > thr) *z0 = i + 1;
+  for (int i = n - 1; i >= n / 2; --i)
+    if (std::fabs(z[i]) > thr) *z1 = i;
+  if (!cyclic) {
+    *z0 = 0;
+    *z1 = n;
   }
 }
 
@@ -288,7 +304,8 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
         c->ctab_off[axis][par] = off;
         double* base = c->ctab_host.data() + off;
         compact_table(n, p->compact_alpha, cyclic, par ? -1.0 : 1.0, base, base + n, base + 2 * n,
-                      &c->cfac[axis][par], &c->cden[axis][par], &c->cflat[axis][par]);
+                      &c->cfac[axis][par], &c->cden[axis][par], &c->cflat[axis][par],
+                      &c->cz0[axis][par], &c->cz1[axis][par]);
         off += 3 * (size_t)n;
       }
     }

@@ -42,11 +42,12 @@ struct lbm2p_ctx {
   // the workspace (device) and their host image, coefficients a_n
   void* cscratch;
   double* ctab_dev;
-  double* cfct;  // per-line Sherman-Morrison factors (3 ny x-lines, 3 nx y-lines)
+  double* cfct;  // room for the FP32 copy of the tables (6 (nx + ny) floats)
   std::vector<double> ctab_host;
   double ca[6];
   double cfac[2][2], cden[2][2];
   int cflat[2][2];        // first index of the tables' constant run (per axis, parity)
+  int cz0[2][2], cz1[2][2];  // z_i negligible for cz0 <= i < cz1 (per axis, parity)
   size_t ctab_off[2][2];  // offsets (in doubles) of each (axis, parity) table
   int ctab_n[2];
   int ctab_uploaded;

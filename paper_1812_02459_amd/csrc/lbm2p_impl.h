@@ -407,74 +407,72 @@ struct ProfScope {
   }
 };
 
+// the tables in the kernels' precision: FP64 reads the host's tables as
+// uploaded, FP32 a copy rounded once (uploaded with them, in the room after)
 template <typename T>
 CompactArgs<T> compact_args(const lbm2p_ctx* c) {
   CompactArgs<T> A;
   for (int k = 0; k < 6; ++k) A.a[k] = c->ca[k];
   A.alpha = c->p.compact_alpha;
+  const T* dev = sizeof(T) == 8 ? (const T*)c->ctab_dev : (const T*)c->cfct;
   for (int axis = 0; axis < 2; ++axis)
     for (int par = 0; par < 2; ++par) {
       const int n = c->ctab_n[axis];
-      const double* base = c->ctab_dev + c->ctab_off[axis][par];
+      const T* base = dev + c->ctab_off[axis][par];
       const int K = c->cflat[axis][par];
       const double* h = c->ctab_host.data() + c->ctab_off[axis][par];
-      A.line[axis][par] = CompactLine{base, base + n, base + 2 * n, c->cfac[axis][par],
-                                      c->cden[axis][par],
-                                      axis == 0 ? !c->p.wall_x : !c->p.wall_y, K,
-                                      n >= 2 ? h[K] : 0.0, n >= 2 ? h[n + K] : 0.0};
+      CompactLine<T>& L = A.line[axis][par];
+      L.cp = base;
+      L.inv = base + n;
+      L.z = base + 2 * n;
+      L.fac = T(c->cfac[axis][par]);
+      L.den = T(c->cden[axis][par]);
+      L.cyclic = axis == 0 ? !c->p.wall_x : !c->p.wall_y;
+      L.K = K;
+      L.Z0 = c->cz0[axis][par];
+      L.Z1 = c->cz1[axis][par];
+      L.cp_lim = T(n >= 2 ? h[K] : 0.0);
+      L.inv_lim = T(n >= 2 ? h[n + K] : 0.0);
     }
   return A;
 }
 
-// Chunk length (log2) per thread of an x-line of nx nodes on NWV waves: the
-// power of two >= nx / (64 NWV); and the line's padded LDS size.
-template <int NWV>
-inline int cline_lg(int nx) {
-  int lg = 0;
-  while ((64 * NWV << lg) < nx) ++lg;
-  return lg;
-}
-template <typename T, int NWV>
-inline size_t cline_lds(int nx) {
-  const int lg = cline_lg<NWV>(nx);
-  return ((size_t)nx + ((size_t)nx >> lg) + 1) * sizeof(T);
-}
-
-template <typename T, int N, int NWV>
-void launch_cline_x(lbm2p_ctx* c, const CompactArgs<T>& A, const T* p, const T* ux, const T* uy,
-                    T* fx) {
+// x-lines of n nodes: one workgroup per (line, field) of NT threads with
+// chunks of M nodes, the smallest of the shapes that covers the line
+template <typename T, int N, int NT, int M>
+void launch_cx(lbm2p_ctx* c, const CompactArgs<T>& A, const T* p, const T* ux, const T* uy,
+               T* fx) {
   const int nx = c->p.nx, ny = c->p.ny;
   const long long ps = c->ps;
-  k_cline<T, N, NWV><<<3 * ny, 64 * NWV, cline_lds<T, NWV>(nx), c->stream>>>(
-      A, A.line[0][0], A.line[0][1], p, ux, uy, fx, fx + ps, fx + 2 * ps, c->cfct, nx, ny,
-      c->p.wall_x, cline_lg<NWV>(nx));
+  k_cx<T, N, NT, M><<<3 * ny, NT, cx_lds<T, N, NT, M>(), c->stream>>>(
+      A, p, ux, uy, fx, fx + ps, fx + 2 * ps, nx, ny, c->p.wall_x);
 }
 
 template <typename T, int N>
 void launch_compact(lbm2p_ctx* c, const KParams<T>& K, const T* p, const T* ux, const T* uy,
                     T* po, T* uxo, T* uyo) {
   const CompactArgs<T> A = compact_args<T>(c);
-  const int nx = c->p.nx;
-  T* scr = (T*)c->cscratch;  // d of the y-lines (three fields)
+  const int nx = c->p.nx, ny = c->p.ny;
+  T* scr = (T*)c->cscratch;  // chunk coefficients and carries of the y-lines
   T* fx = scr + 3 * c->ps;   // F_x of the three fields
-  // x-lines: 4 waves per line; FP64 lines take 8 when the padded line fits in
-  // 64 KB of LDS (measured faster at 4096 in FP64, slower in FP32)
-  if (sizeof(T) == 8 && cline_lds<T, 8>(nx) <= 65536)
-    launch_cline_x<T, N, 8>(c, A, p, ux, uy, fx);
+  if (nx <= 64 * 16)
+    launch_cx<T, N, 64, 16>(c, A, p, ux, uy, fx);
+  else if (nx <= 512 * 8)
+    launch_cx<T, N, 512, 8>(c, A, p, ux, uy, fx);
   else
-    launch_cline_x<T, N, 4>(c, A, p, ux, uy, fx);
-  // y-lines: 16 waves per workgroup, CW columns per workgroup.  FP32 lattices
-  // wide enough to give every CU a workgroup take whole 256-byte row segments
-  // (CW = 64: 0.73 against 0.79 ms per application at 4096^2); narrower ones,
-  // and FP64, take 16 columns, which keeps 4x more workgroups in flight (at
-  // 256 x 1024 the 64-column launch has 12 workgroups and is 50 % slower).
-  constexpr int NW = 16;
-  if (sizeof(T) == 4 && 3 * (nx / 64) >= 128)
-    k_cline_y<T, N, NW, 64><<<dim3((nx + 63) / 64, 3), 64 * NW, 0, c->stream>>>(
-        K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
-  else
-    k_cline_y<T, N, NW, 16><<<dim3((nx + 15) / 16, 3), 64 * NW, 0, c->stream>>>(
-        K, A, p, ux, uy, fx, scr, c->cfct, po, uxo, uyo);
+    launch_cx<T, N, 512, 16>(c, A, p, ux, uy, fx);
+  // y-lines: chunks of MY = 16 rows (32 rows in FP32 measured slower: their
+  // registers halve the waves in flight), one chunk row range of 256 columns
+  // per workgroup
+  constexpr int MY = 16;
+  const int nch = (ny + MY - 1) / MY;
+  // after the three fields' planes; 3 (7 nch + 1) nx <= 3 nx ny for ny >= 16
+  T* fct = scr + 3 * (long long)CY_PLANES * nch * nx;
+  const dim3 grid((nx + 255) / 256, nch, 3);
+  k_cy_maps<T, N, MY><<<grid, 256, 0, c->stream>>>(K, A, p, ux, uy, scr, nch);
+  k_cy_scan<T, 16><<<dim3((nx + 63) / 64, 3), 1024, 0, c->stream>>>(K, A, scr, fct, nch);
+  k_cy_apply<T, N, MY><<<grid, 256, 0, c->stream>>>(K, A, p, ux, uy, fx, scr, fct, po, uxo, uyo,
+                                                    nch);
 }
 
 // Populations larger than the last-level cache (256 MB): the gather and the
@@ -741,9 +739,18 @@ template <typename T>
 int init_impl(lbm2p_ctx* c, const double* phi0, const double* ux0, const double* uy0,
               const double* p0) {
   if (c->ctab_dev && !c->ctab_uploaded) {
-    if (hipMemcpyAsync(c->ctab_dev, c->ctab_host.data(), c->ctab_host.size() * sizeof(double),
+    // the FP64 tables (2 parities x 3 per axis), and in FP32 their rounded copy
+    const size_t nt = 2 * 3 * ((size_t)c->p.nx + (size_t)c->p.ny);
+    std::vector<float> t32;
+    if (hipMemcpyAsync(c->ctab_dev, c->ctab_host.data(), nt * sizeof(double),
                        hipMemcpyHostToDevice, c->stream) != hipSuccess)
       return LBM2P_EHIP;
+    if (sizeof(T) == 4) {
+      t32.assign(c->ctab_host.begin(), c->ctab_host.begin() + nt);
+      if (hipMemcpyAsync(c->cfct, t32.data(), nt * sizeof(float), hipMemcpyHostToDevice,
+                         c->stream) != hipSuccess)
+        return LBM2P_EHIP;
+    }
     if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM2P_EHIP;
     c->ctab_uploaded = 1;
   }

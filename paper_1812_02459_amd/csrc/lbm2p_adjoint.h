@@ -35,7 +35,14 @@
 
 #include "lbm2p_kernels.h"
 
+
 namespace lbm2p {
+
+// The reverse passes may contract a * b + c into fused multiply-adds in FP64
+// too: their results are compared within a tolerance, not bit for bit, while
+// the FP64 forward kernels of the same unit round exactly as written.  Scoped
+// to the function bodies that start with it.
+#define LBM2P_ADJ_CONTRACT _Pragma("clang fp contract(fast)")
 
 // derivatives of the derived constants with respect to sigma and M
 // (kappa = 3 sigma W / 8, 4 beta = 3 sigma / W, eta = 3 M / (tau_f - 1/2),
@@ -54,26 +61,44 @@ template <typename T, int NT, int RW, int RH>
 __device__ __forceinline__ void load_par(T* dst, const T* __restrict__ src,
                                          const T* __restrict__ src2, int gx0, int gy0,
                                          const KParams<T>& P, int sx, int sy) {
-  constexpr int N = RW * RH, IT = (N + NT - 1) / NT;
-  T v[IT];
+  using WS = WinSlots<NT, RW, RH>;
+  constexpr int NV = WS::NV;
+  T v[NV];
+  if (gx0 >= 0 && gx0 + RW <= P.nx && gy0 >= 0 && gy0 + RH <= P.ny) {
+    // inside the lattice: plain row addresses, no mirror
+    const T* __restrict__ base = src + (gy0 * P.nx + gx0);
+    const T* __restrict__ base2 = src2 ? src2 + (gy0 * P.nx + gx0) : nullptr;
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int idx = (int)threadIdx.x + k * NT;
-    if (idx < N) {
-      const int ly = idx / RW, lx = idx - ly * RW;
+    for (int n = 0; n < NV; ++n) {
+      int lx, ly;
+      bool in;
+      WS::at(n, lx, ly, in);
+      const int o = ly * P.nx + lx;
+      T w = base[o];
+      if (base2) w = w + base2[o];
+      v[n] = w;
+    }
+  } else {
+#pragma unroll
+    for (int n = 0; n < NV; ++n) {
+      int lx, ly;
+      bool in;
+      WS::at(n, lx, ly, in);
       int fx = 0, fy = 0;
       const int x = map_idx(gx0 + lx, P.nx, P.wx, fx);
       const int y = map_idx(gy0 + ly, P.ny, P.wy, fy);
       const int o = y * P.nx + x;
       T w = src[o];
       if (src2) w = w + src2[o];
-      v[k] = ((fx && sx < 0) != (fy && sy < 0)) ? -w : w;
+      v[n] = ((fx && sx < 0) != (fy && sy < 0)) ? -w : w;
     }
   }
 #pragma unroll
-  for (int k = 0; k < IT; ++k) {
-    const int idx = (int)threadIdx.x + k * NT;
-    if (idx < N) dst[idx] = v[k];
+  for (int n = 0; n < NV; ++n) {
+    int lx, ly;
+    bool in;
+    WS::at(n, lx, ly, in);
+    if (in) dst[ly * RW + lx] = v[n];
   }
 }
 
@@ -101,6 +126,7 @@ __device__ __forceinline__ ERead<T> eread(const T* a, const KParams<T>& P, bool 
 // (M^T v)_i = sum_k M_ki v_k
 template <typename T>
 __device__ __forceinline__ void mT_apply(const T v[9], T out[9]) {
+  LBM2P_ADJ_CONTRACT
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     T acc = T(0);
@@ -121,6 +147,7 @@ __device__ __forceinline__ void mT_apply(const T v[9], T out[9]) {
 template <typename T>
 __device__ __forceinline__ void mrt_collide_adj(const T y[9], const T s[9], T fbar[9], T feqb[9],
                                                 T Fb[9], T r[9]) {
+  LBM2P_ADJ_CONTRACT
   T my[9], sr[9], hr[9];
   m_apply(y, my);
 #pragma unroll
@@ -139,6 +166,7 @@ __device__ __forceinline__ void mrt_collide_adj(const T y[9], const T s[9], T fb
 template <typename T>
 __device__ __forceinline__ void f_eq_adj(T phi, T mu, T ux, T uy, T eta, const T fb[9], T& phb,
                                          T& mub, T& ubx, T& uby, T& etab) {
+  LBM2P_ADJ_CONTRACT
   const T usq = ux * ux + uy * uy;
   const T w0 = T(w_of(0));
   phb = phb + fb[0] * (T(1) - (w0 * usq) * T(1.5));
@@ -168,6 +196,7 @@ __device__ __forceinline__ void f_eq_adj(T phi, T mu, T ux, T uy, T eta, const T
 // reverse of g_eq (eq:geq): adds to pb, ubx, uby
 template <typename T>
 __device__ __forceinline__ void g_eq_adj(T ux, T uy, const T gb[9], T& pb, T& ubx, T& uby) {
+  LBM2P_ADJ_CONTRACT
   T usqb = T(0), cx = T(0), cy = T(0), sp = T(0);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -188,6 +217,7 @@ __device__ __forceinline__ void g_eq_adj(T ux, T uy, const T gb[9], T& pb, T& ub
 template <typename T>
 __device__ __forceinline__ void src_f_adj(T phi, T ax, T ay, const T Fb[9], T& phb, T& abx,
                                           T& aby) {
+  LBM2P_ADJ_CONTRACT
   T cx = T(0), cy = T(0);
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
@@ -205,6 +235,7 @@ __device__ __forceinline__ void src_f_adj(T phi, T ax, T ay, const T Fb[9], T& p
 template <typename T>
 __device__ __forceinline__ void src_g_adj(T ux, T uy, T bx, T by, const T Gb[9], T& Frbx,
                                           T& Frby, T& ubx, T& uby, T& bbx, T& bby) {
+  LBM2P_ADJ_CONTRACT
   T ubb = T(0), fx = T(0), fy = T(0), ux_ = T(0), uy_ = T(0), bx_ = T(0), by_ = T(0);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
@@ -238,6 +269,7 @@ __device__ __forceinline__ void src_g_adj(T ux, T uy, T bx, T by, const T Gb[9],
 // The clamp passes the derivative for -1 <= phi <= 1 (ends included).
 template <typename T>
 __device__ __forceinline__ T props_adj(T phi, T rho, T nu, T rhob, T nub, const KParams<T>& P) {
+  LBM2P_ADJ_CONTRACT
   if (!(phi >= T(-1) && phi <= T(1))) return T(0);
   const T rb = rhob - (nub * nu) / rho;
   const T mb = nub / rho;
@@ -259,6 +291,7 @@ __device__ __forceinline__ void force_fwd(const Tile<T>& tP, const Tile<T>& tPx,
                                           const Tile<T>& tMu, const Tile<T>& tRho,
                                           const Tile<T>& tUx, const Tile<T>& tUy, T p, int x, int y,
                                           const KParams<T>& P, ForceFwd<T>& f) {
+  LBM2P_ADJ_CONTRACT
   const T phi = tP(x, y);
   f.rho = density<T>(phi, P.rho1, P.rho2);
   f.nu = kin_visc<T>(phi, f.rho, P.mu1, P.mu2);
@@ -293,6 +326,7 @@ struct ForceAdj {
 template <typename T>
 __device__ __forceinline__ void force_adj(const ForceFwd<T>& f, T p, T Fbx, T Fby,
                                           const KParams<T>& P, ForceAdj<T>& a) {
+  LBM2P_ADJ_CONTRACT
   // F_p = -p grad rho
   a.p = -(Fbx * f.grx + Fby * f.gry);
   T grx = -(p * Fbx), gry = -(p * Fby);
@@ -376,6 +410,7 @@ __global__ __launch_bounds__(NT) void k_adj_collide(
     const T* __restrict__ pp, const T* __restrict__ pjx, const T* __restrict__ pjy,
     T* __restrict__ Afo, T* __restrict__ Ago, T* __restrict__ Uox, T* __restrict__ Uoy,
     AdjWork<T> Wk) {
+  LBM2P_ADJ_CONTRACT
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int NC = COUPLED ? W1 * H1 : 1, NP = PEND ? W1 * H1 : 1,
                 NPC = (PEND && COUPLED) ? W1 * H1 : 1;
@@ -404,10 +439,10 @@ __global__ __launch_bounds__(NT) void k_adj_collide(
   if (COUPLED) {
     derived_halo1<T, NT, W1, H1>(tP, sPx, sPy, sMu, sRho, P);
   } else {
-    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+    for_window<W1, H1, NT>([&](int ix_, int iy_) {
+      const int ly = iy_ - 1, lx = ix_ - 1, idx = iy_ * W1 + ix_;
       sMu[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
-    }
+    });
   }
   __syncthreads();
   const Tile<T> tPx{sPx, W1, 1}, tPy{sPy, W1, 1}, tMu{sMu, W1, 1}, tRho{sRho, W1, 1},
@@ -540,6 +575,7 @@ __global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
                                                      const T* __restrict__ Uoix,
                                                      const T* __restrict__ Uoiy, AdjWork<T> Wk,
                                                      T* op, T* oux, T* ouy) {
+  LBM2P_ADJ_CONTRACT
   constexpr int WN = TX + 2 * N, HN = TY + 2 * N, WB = WN + 2, HB = HN + 2;
   __shared__ T sB[2][WB * HB];
   __shared__ T sPt[WN * HN], sUx[WN * HN], sUy[WN * HN];
@@ -563,10 +599,10 @@ __global__ __launch_bounds__(NT) void k_adj_filter_t(KParams<T> P, int tiles_x,
                     psx[2 * k + 1], psy[2 * k + 1]);
     __syncthreads();
     T* d = k == 0 ? sUx : (k == 1 ? sUy : sPt);
-    for (int idx = threadIdx.x; idx < WN * HN; idx += NT) {
-      const int ly = idx / WN - N, lx = idx % WN - N;
+    for_window<WN, HN, NT>([&](int ix_, int iy_) {
+      const int ly = iy_ - N, lx = ix_ - N, idx = iy_ * WN + ix_;
       d[idx] = d[idx] - (iso_grad_x<T>(tB0, lx, ly) + iso_grad_y<T>(tB1, lx, ly));
-    }
+    });
   }
   __syncthreads();
   T dd[N + 1];
@@ -610,6 +646,7 @@ __global__ __launch_bounds__(NT) void k_adj_vel(KParams<T> P, AdjConst C, int ti
                                                  const T* __restrict__ ukx,
                                                  const T* __restrict__ uky, int src,
                                                  AdjWork<T> Wk) {
+  LBM2P_ADJ_CONTRACT
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int NR = (TX * TY + NT - 1) / NT;
   __shared__ T sP[W2 * H2];
@@ -702,6 +739,7 @@ __global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int ti
                                                 const double* __restrict__ seed,
                                                 T* __restrict__ Uox, T* __restrict__ Uoy,
                                                 AdjWork<T> Wk) {
+  LBM2P_ADJ_CONTRACT
   constexpr int W2 = TX + 4, H2 = TY + 4, W1 = TX + 2, H1 = TY + 2;
   constexpr int NR = (TX * TY + NT - 1) / NT;
   constexpr int NQ = COUPLED ? W1 * H1 : 1, NB = COUPLED ? W2 * H2 : 1;
@@ -728,8 +766,8 @@ __global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int ti
       load_par<T, NT, W2, H2>(sB[1], s2[2 * k + 1], nullptr, x0 - 2, y0 - 2, P, p2x[2 * k + 1],
                       p2y[2 * k + 1]);
       __syncthreads();
-      for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-        const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+      for_window<W1, H1, NT>([&](int ix_, int iy_) {
+        const int ly = iy_ - 1, lx = ix_ - 1, idx = iy_ * W1 + ix_;
         if (k == 0) {
           sMu[idx] = sMu[idx] - (iso_grad_x<T>(tA, lx, ly) + iso_grad_y<T>(tC, lx, ly));
         } else if (k == 1) {
@@ -738,18 +776,18 @@ __global__ __launch_bounds__(NT) void k_adj_phi(KParams<T> P, AdjConst C, int ti
         } else {
           sQxy[idx] = -(iso_grad_x<T>(tA, lx, ly) + iso_grad_y<T>(tC, lx, ly));
         }
-      }
+      });
     }
     __syncthreads();
     // (d_x phi, d_y phi) adjoints on halo 1, in place of the Q_xx, Q_yy adjoints
-    for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-      const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+    for_window<W1, H1, NT>([&](int ix_, int iy_) {
+      const int ly = iy_ - 1, lx = ix_ - 1, idx = iy_ * W1 + ix_;
       T px, py;
       iso_grad<T>(tP, lx, ly, px, py);
       const T qxx = sQxx[idx], qyy = sQyy[idx], qxy = sQxy[idx];
       sQxx[idx] = (T(2) * px) * qxx + py * qxy;
       sQyy[idx] = (T(2) * py) * qyy + px * qxy;
-    }
+    });
     // tile-only accumulations from halo-1 windows: rho_bar, and u^0_bar
     const Tile<T> tA1{sB[0], W1, 1}, tC1{sB[1], W1, 1};
     const T* const s1[6] = {Wk.a_grx, Wk.a_gry, du_sel(Wk, src, 0), du_sel(Wk, src, 1),
@@ -815,6 +853,7 @@ __global__ __launch_bounds__(NT) void k_adj_fd(KParams<T> P, AdjConst C, int til
                                                 const T* __restrict__ in,
                                                 const T* __restrict__ src, T coef,
                                                 AdjWork<T> Wk) {
+  LBM2P_ADJ_CONTRACT
   constexpr int W6 = TX + 12, H6 = TY + 12;   // phi_s
   constexpr int W5 = TX + 10, H5 = TY + 10;   // a, mu (then mu_bar on halo 1)
   constexpr int W3 = TX + 6, H3 = TY + 6;     // pointwise adjoints
@@ -828,13 +867,13 @@ __global__ __launch_bounds__(NT) void k_adj_fd(KParams<T> P, AdjConst C, int til
   load_par<T, NT, W5, H5>(sA, src, nullptr, x0 - 5, y0 - 5, P, 1, 1);
   __syncthreads();
   const Tile<T> tP{sP, W6, 6}, tA{sA, W5, 5}, tM{sM, W5, 5};
-  for (int idx = threadIdx.x; idx < W5 * H5; idx += NT) {
-    const int ly = idx / W5 - 5, lx = idx % W5 - 5;
+  for_window<W5, H5, NT>([&](int ix_, int iy_) {
+    const int ly = iy_ - 5, lx = ix_ - 5, idx = iy_ * W5 + ix_;
     sM[idx] = chem_pot<T>(tP, lx, ly, P.c4b, P.kappa);
-  }
+  });
   __syncthreads();
-  for (int idx = threadIdx.x; idx < W3 * H3; idx += NT) {
-    const int ly = idx / W3 - 3, lx = idx % W3 - 3;
+  for_window<W3, H3, NT>([&](int ix_, int iy_) {
+    const int ly = iy_ - 3, lx = ix_ - 3, idx = iy_ * W3 + ix_;
     const T Jbx = coef * (-d4<T>(tA(lx - 2, ly), tA(lx - 1, ly), tA(lx + 1, ly), tA(lx + 2, ly)));
     const T Jby = coef * (-d4<T>(tA(lx, ly - 2), tA(lx, ly - 1), tA(lx, ly + 1), tA(lx, ly + 2)));
     const T Gx = d4<T>(tP(lx - 2, ly), tP(lx - 1, ly), tP(lx + 1, ly), tP(lx + 2, ly));
@@ -864,17 +903,17 @@ __global__ __launch_bounds__(NT) void k_adj_fd(KParams<T> P, AdjConst C, int til
       const long long id = (long long)(y0 + ly) * P.nx + (x0 + lx);
       Wk.dM[id] = Wk.dM[id] - double(s * qn);  // dL/dM = -dL/d(-M); one thread per node
     }
-  }
+  });
   __syncthreads();
   const Tile<T> tGx{sGx, W3, 3}, tGy{sGy, W3, 3}, tMx{sMx, W3, 3}, tMy{sMy, W3, 3},
       tL{sL, W3, 3};
   // mu_bar on halo 1, over the (now free) mu tile
   T* sMb = sM;
-  for (int idx = threadIdx.x; idx < W1 * H1; idx += NT) {
-    const int ly = idx / W1 - 1, lx = idx % W1 - 1;
+  for_window<W1, H1, NT>([&](int ix_, int iy_) {
+    const int ly = iy_ - 1, lx = ix_ - 1, idx = iy_ * W1 + ix_;
     sMb[idx] = -d4<T>(tMx(lx - 2, ly), tMx(lx - 1, ly), tMx(lx + 1, ly), tMx(lx + 2, ly)) -
                d4<T>(tMy(lx, ly - 2), tMy(lx, ly - 1), tMy(lx, ly + 1), tMy(lx, ly + 2));
-  }
+  });
   __syncthreads();
   const Tile<T> tMb{sMb, W1, 1};
   for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
@@ -909,6 +948,7 @@ template <typename T, bool COUPLED>
 __global__ __launch_bounds__(256) void k_adj_gather(KParams<T> P, const T* __restrict__ phib_b,
                                                     T* __restrict__ Afo, T* __restrict__ Ago,
                                                     AdjWork<T> Wk) {
+  LBM2P_ADJ_CONTRACT
   const long long n = (long long)P.nx * P.ny;
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
@@ -937,6 +977,7 @@ __global__ __launch_bounds__(256) void k_adj_init_a(KParams<T> P, AdjConst C,
                                                     const double* __restrict__ ux0,
                                                     const double* __restrict__ uy0,
                                                     const T* __restrict__ Af, AdjWork<T> Wk) {
+  LBM2P_ADJ_CONTRACT
   const long long n = (long long)P.nx * P.ny;
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
@@ -1018,3 +1059,4 @@ __global__ __launch_bounds__(256) void k_sum2(const double* __restrict__ part, i
 }  // namespace
 
 }  // namespace lbm2p
+

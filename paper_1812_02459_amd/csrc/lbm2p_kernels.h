@@ -154,16 +154,18 @@ __device__ __forceinline__ T& fld(T* base, long long k) {
 // the lattice (most tiles) takes plain row addresses; only windows that cross
 // an edge map each index through the wrap or mirror.  Node indices fit in 32
 // bits (checked at context creation).
-template <typename T, typename S, int NT, int RW, int RH>
-__device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, int gx0, int gy0,
-                                            const KParams<T>& P, bool odd) {
+// Slots of a thread in a (RW x RH) window, in for_window's element order:
+// slot n (compile-time after unrolling) -> element (lx, ly) and whether it is
+// one of the window's (a slot beyond the last row names an element of that
+// row instead, so that a load through it stays in bounds).
+template <int NT, int RW, int RH>
+struct WinSlots {
+  static constexpr int NW = NT / 64, NC = RW / 64, R = RW % 64, RR = R > 0 ? R : 1;
+  static constexpr int KR = (RH + NW - 1) / NW, KT = R > 0 ? (R * RH + NT - 1) / NT : 0;
+  static constexpr int NV = NC * KR + KT;
   static_assert(NT % 64 == 0, "whole wavefronts");
-  constexpr int NW = NT / 64, NC = RW / 64, R = RW % 64, RR = R > 0 ? R : 1;
-  constexpr int KR = (RH + NW - 1) / NW, KT = R > 0 ? (R * RH + NT - 1) / NT : 0;
-  constexpr int NV = NC * KR + KT;
-  const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
-  // slot n (compile-time after unrolling) -> element (lx, ly), in the window or not
-  auto coords = [&](int n, int& lx, int& ly, bool& in) {
+  __device__ __forceinline__ static void at(int n, int& lx, int& ly, bool& in) {
+    const int lane = (int)threadIdx.x & 63, wv = (int)threadIdx.x >> 6;
     if (n < NC * KR) {
       lx = (n / KR) * 64 + lane;
       ly = wv + (n % KR) * NW;
@@ -176,7 +178,15 @@ __device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, i
       lx = NC * 64 + j % RR;
       ly = j / RR;
     }
-  };
+  }
+};
+
+template <typename T, typename S, int NT, int RW, int RH>
+__device__ __forceinline__ void load_window(T* dst, const S* __restrict__ src, int gx0, int gy0,
+                                            const KParams<T>& P, bool odd) {
+  using WS = WinSlots<NT, RW, RH>;
+  constexpr int NV = WS::NV;
+  auto coords = [](int n, int& lx, int& ly, bool& in) { WS::at(n, lx, ly, in); };
   T v[NV];
   if (gx0 >= 0 && gx0 + RW <= P.nx && gy0 >= 0 && gy0 + RH <= P.ny) {
     const S* __restrict__ base = src + (gy0 * P.nx + gx0);

@@ -342,6 +342,7 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   c->track_resid = 0;
   c->res_valid = 0;
   c->vpend = 0;
+  c->adj_stream = nullptr;
   *out = c;
   return LBM2P_OK;
 }
@@ -350,6 +351,8 @@ void lbm2p_destroy(lbm2p_ctx* c) {
   if (!c) return;
   for (auto e : c->ev0) hipEventDestroy(e);
   for (auto e : c->ev1) hipEventDestroy(e);
+  for (auto e : c->adj_ev) hipEventDestroy(e);
+  if (c->adj_stream) hipStreamDestroy(c->adj_stream);
   delete c;
 }
 

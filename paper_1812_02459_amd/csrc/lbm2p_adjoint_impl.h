@@ -391,30 +391,93 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
   const OwnPlanes own = own_planes(c);
   int ai = 0;
   Pending<T> pd{nullptr, nullptr, nullptr, nullptr};
-  for (int seg = A.L.nseg - 1; seg >= 0; --seg) {
-    const int s0 = seg * k;
-    const int len = std::min(k, nsteps - s0);
-    if (seg == A.L.nseg - 1 && c->adj_last_kept) {
+  const int nseg = A.L.nseg;
+  // Segment s keeps its step j in slot m(s, j): the last segment in step
+  // order, the ones before it alternating.  The recompute of segment s - 1
+  // (forward in time) then fills slot m(s - 1, i) = the slot the reverse of
+  // segment s (backward in time) releases at its step k - 1 - i, so with a
+  // second stream the two run side by side, each recomputed step waiting only
+  // for the reverse step that frees its slot.  The recomputes use the
+  // context's planes and the reverse sweep does not (coupled step, explicit
+  // filter: the compact filter's scratch is shared, so it takes one stream).
+  auto slot_of = [&](int s, int j) { return ((nseg - 1 - s) & 1) ? k - 1 - j : j; };
+  auto seg_len = [&](int s) { return std::min(k, nsteps - s * k); };
+  bool overlap = p.coupled && !p.compact && nseg > 1;
+  if (overlap && !c->adj_stream &&
+      hipStreamCreateWithFlags(&c->adj_stream, hipStreamNonBlocking) != hipSuccess) {
+    c->adj_stream = nullptr;
+    overlap = false;
+  }
+  while (overlap && c->adj_ev.size() < (size_t)k + 2) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      overlap = false;
+      break;
+    }
+    c->adj_ev.push_back(e);
+  }
+  hipStream_t sb = overlap ? c->adj_stream : st;
+  // recompute of segment s on stream sb: its checkpoint, then step by step
+  auto recompute_begin = [&](int s) {
+    restore_planes(c, own);
+    c->stream = sb;
+    load_ckpt<T>(c, A, s, c->adj_parity0 ^ ((s * k) & 1), false);
+    c->stream = st;
+  };
+  auto recompute_step = [&](int s, int i) {
+    c->stream = sb;
+    c->rec = 1;
+    bind_slot<T>(c, A, slot_of(s, i));
+    const int e = step_impl<T>(c, 1);
+    c->rec = 0;
+    c->stream = st;
+    return e;
+  };
+  auto fail = [&](int e) {
+    c->stream = st;
+    c->rec = 0;
+    restore_planes(c, own);
+    if (overlap) hipStreamSynchronize(sb);
+    return e;
+  };
+  if (nseg > 0) {
+    if (c->adj_last_kept) {
       // kept by the record; the recomputes below reuse the slots
-      if (A.L.nseg > 1) c->adj_last_kept = 0;
+      if (nseg > 1) c->adj_last_kept = 0;
     } else {
-      restore_planes(c, own);
-      load_ckpt<T>(c, A, seg, c->adj_parity0 ^ (s0 & 1), false);
-      c->rec = 1;
-      for (int j = 0; j < len; ++j) {
-        bind_slot<T>(c, A, j);
-        const int e = step_impl<T>(c, 1);
-        if (e) {
-          c->rec = 0;
-          restore_planes(c, own);
-          return e;
-        }
+      hipStream_t keep = sb;
+      sb = st;
+      recompute_begin(nseg - 1);
+      for (int i = 0; i < seg_len(nseg - 1); ++i) {
+        const int e = recompute_step(nseg - 1, i);
+        if (e) return fail(e);
+      }
+      sb = keep;
+    }
+  }
+  if (overlap) {
+    // the second stream starts after everything issued so far
+    if (hipEventRecord(c->adj_ev[k], st) != hipSuccess ||
+        hipStreamWaitEvent(sb, c->adj_ev[k], 0) != hipSuccess)
+      return fail(LBM2P_EHIP);
+  }
+  for (int seg = nseg - 1; seg >= 0; --seg) {
+    const int s0 = seg * k;
+    const int len = seg_len(seg);
+    const T* cku = A.ckpt(seg) + (size_t)9 * (p.coupled ? 2 : 1) * ps;
+    // the recompute of the segment before, alongside (its steps whose slots
+    // this segment leaves unused start at once)
+    const bool pre = overlap && seg > 0;
+    int inext = 0;
+    if (pre) {
+      recompute_begin(seg - 1);
+      for (; inext < seg_len(seg - 1) && k - 1 - inext >= len; ++inext) {
+        const int e = recompute_step(seg - 1, inext);
+        if (e) return fail(e);
       }
     }
-    c->rec = 0;
-    const T* cku = A.ckpt(seg) + (size_t)9 * (p.coupled ? 2 : 1) * ps;
     for (int j = len - 1; j >= 0; --j) {
-      const Slot<T> sl = A.slot(j, p);
+      const Slot<T> sl = A.slot(slot_of(seg, j), p);
       const T* uox = nullptr;
       const T* uoy = nullptr;
       if (p.coupled) {
@@ -422,7 +485,7 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
           uox = cku;
           uoy = cku + ps;
         } else {
-          const Slot<T> pr = A.slot(j - 1, p);
+          const Slot<T> pr = A.slot(slot_of(seg, j - 1), p);
           uox = pr.utx;
           uoy = pr.uty;
         }
@@ -430,6 +493,26 @@ int adjoint_impl(lbm2p_ctx* c, lbm2p_adjoint_io* io) {
       const double* seed = (s0 + j == nsteps - 1) ? io->dL_dphi : nullptr;
       pd = adj_step<T>(c, A, Wk, sl, uox, uoy, seed, ai, pd);
       ai = 1 - ai;
+      if (pre && k - 1 - j == inext && inext < seg_len(seg - 1)) {
+        // slot m(seg, j) released: the recompute step that fills it
+        if (hipEventRecord(c->adj_ev[j], st) != hipSuccess ||
+            hipStreamWaitEvent(sb, c->adj_ev[j], 0) != hipSuccess)
+          return fail(LBM2P_EHIP);
+        const int e = recompute_step(seg - 1, inext++);
+        if (e) return fail(e);
+      }
+    }
+    if (pre) {
+      // the reverse of the segment before waits for its recompute
+      if (hipEventRecord(c->adj_ev[k + 1], sb) != hipSuccess ||
+          hipStreamWaitEvent(st, c->adj_ev[k + 1], 0) != hipSuccess)
+        return fail(LBM2P_EHIP);
+    } else if (seg > 0) {
+      recompute_begin(seg - 1);
+      for (int i = 0; i < seg_len(seg - 1); ++i) {
+        const int e = recompute_step(seg - 1, i);
+        if (e) return fail(e);
+      }
     }
   }
   // back to the context's own planes and the recorded final state

@@ -66,6 +66,10 @@ struct lbm2p_ctx {
   int adj_nsteps, adj_k, adj_from_init, adj_parity0, adj_ready;
   int adj_last_kept;            // the slots hold the last recorded segment
   long long adj_steps_end;
+  // adjoint: a second stream for the segment recomputes, and events ordering
+  // them against the reverse sweep (created at the first adjoint that uses them)
+  hipStream_t adj_stream;
+  std::vector<hipEvent_t> adj_ev;
 };
 
 namespace lbm2p {

@@ -666,6 +666,9 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         else if (tv.tx * (long long)tv.ty < TINY_TILES)
           launch_vel<T, TINY_TY, TINY_NT>(
               p, K, st, two, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
+        else if (tv.tx * (long long)tv.ty < VEL_MIN_TILES)
+          launch_vel<T, VelSmall<T>::TY, VelSmall<T>::NT>(
+              p, K, st, two, phi, (T*)c->praw, (T*)c->jx, (T*)c->jy, ux, uy, ox, oy, o1x, o1y);
         else
           launch_vel<T, C::VEL_TY, C::VEL_NT>(p, K, st, two, phi, (T*)c->praw, (T*)c->jx,
                                               (T*)c->jy, ux, uy, ox, oy, o1x, o1y);

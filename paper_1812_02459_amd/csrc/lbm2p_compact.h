@@ -142,23 +142,33 @@ __global__ __launch_bounds__(NT) void k_cx(CompactArgs<T> A, const T* __restrict
   const long long b = (long long)line * n;
   const int t = (int)threadIdx.x;
   auto pos = [](int e) { return e + e / M; };
-  // the extended line: element e holds chi(e - N)
-  for (int e = t; e < n + 2 * N; e += NT) {
-    const int i = e - N;
-    T v;
-    if (i >= 0 && i < n) {
-      v = src[b + i];
-    } else {
-      int flip = 0;
-      const int k = map_idx(i, n, wall, flip);
-      const T w = src[b + k];
-      v = (odd && flip) ? -w : w;
-    }
-    sd[pos(e)] = v;
+  // the extended line: element e holds chi(e - N); every thread's loads are
+  // issued before its LDS stores (one load latency, not one per element), the
+  // ghost indices mapped without a branch around the load
+  constexpr int LPT = (NT * M + 2 * N + NT - 1) / NT;
+  T lv[LPT];
+#pragma unroll
+  for (int q = 0; q < LPT; ++q) {
+    const int i = t + q * NT - N;
+    int flip = 0;
+    const int k = map_idx(i, n, wall, flip);
+    const T w = src[b + k];
+    lv[q] = (odd && flip) ? -w : w;
+  }
+#pragma unroll
+  for (int q = 0; q < LPT; ++q) {
+    const int e = t + q * NT;
+    if (e < n + 2 * N) sd[pos(e)] = lv[q];
   }
   const int i0 = t * M;
   const int m = n - i0 <= 0 ? 0 : (n - i0 < M ? n - i0 : M);   // elements of this chunk
-  T ti[M], tc[M];
+  T ti[M], tc[M], tz[M];
+  // the cyclic correction's z where it is kept (chunks near the line's ends)
+  const bool zk = L.cyclic && m > 0 && (i0 < L.Z0 || i0 + M > L.Z1);
+  if (zk) {
+#pragma unroll
+    for (int k = 0; k < M; ++k) tz[k] = L.z[i0 + k < n ? i0 + k : n - 1];
+  }
   if (i0 >= L.K && i0 + M <= n - 1) {
 #pragma unroll
     for (int k = 0; k < M; ++k) {
@@ -220,10 +230,7 @@ __global__ __launch_bounds__(NT) void k_cx(CompactArgs<T> A, const T* __restrict
     }
     __syncthreads();
     const T fc = (sY[0] + L.fac * sY[1]) / L.den;
-    if (m > 0 && (i0 < L.Z0 || i0 + M > L.Z1)) {
-      T tz[M];
-#pragma unroll
-      for (int k = 0; k < M; ++k) tz[k] = L.z[i0 + k < n ? i0 + k : n - 1];
+    if (zk) {
 #pragma unroll
       for (int k = 0; k < M; ++k) v[k] = v[k] - fc * tz[k];
     }
@@ -488,6 +495,13 @@ __global__ __launch_bounds__(256) void k_cy_apply(KParams<T> P, CompactArgs<T> A
   const int xs = live ? x : nx - 1;
   const int i0 = c * MY, m = n - i0 < MY ? n - i0 : MY;
   cy_tables<T, MY>(L, i0, n, sI, sC, sZ);
+  // F_x of the chunk's rows, loaded ahead of the recurrences
+  T fxv[MY];
+  {
+    const T* __restrict__ fcol = fxf + xs;
+#pragma unroll
+    for (int k = 0; k < MY; ++k) fxv[k] = fcol[(long long)(i0 + k < n ? i0 + k : n - 1) * nx];
+  }
   T v[MY + 2 * N], ch[MY];
   cy_load_rhs<T, N, MY, true>(src, xs, nx, n, i0, m, P.wy, odd, A, v, ch);
   const long long ps = (long long)nch * nx;
@@ -510,13 +524,12 @@ __global__ __launch_bounds__(256) void k_cy_apply(KParams<T> P, CompactArgs<T> A
     }
   if (!live) return;
   const T a = P.fa;
-  const T* __restrict__ fcol = fxf + (long long)i0 * nx + x;
   T* __restrict__ dcol = dst + (long long)i0 * nx + x;
 #pragma unroll
   for (int k = 0; k < MY; ++k)
     if (k < m) {
       const T fy = v[k] - fc * sZ[k];
-      dcol[(long long)k * nx] = ch[k] - a * ((ch[k] - fcol[(long long)k * nx]) + (ch[k] - fy));
+      dcol[(long long)k * nx] = ch[k] - a * ((ch[k] - fxv[k]) + (ch[k] - fy));
     }
 }
 

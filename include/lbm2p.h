@@ -278,7 +278,12 @@ typedef struct lbm2p_adjoint_io {
  * the first.  Synchronises the stream (the two scalars are host values).  The
  * context ends in the recorded final state (phi, u~, p~ and the populations;
  * lbm2p_fields reports an earlier step until the next lbm2p_step).  ESTATE
- * without a matching record (or after a step, init or set_state since). */
+ * without a matching record (or after a step, init or set_state since).
+ * With more than one segment (coupled step, explicit filter) the segments'
+ * recomputes run on a second stream of the context, ordered against the
+ * context's stream by events; the context creates that stream and the events
+ * at its first such call and releases them in lbm2p_destroy (no device memory
+ * is allocated). */
 int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io);
 
 /* Copy bytes from d_src to d_dst (device memory, both 16-byte aligned, not
@@ -289,7 +294,8 @@ int lbm2p_adjoint(lbm2p_ctx* c, lbm2p_adjoint_io* io);
  * overlapping buffers; EHIP for a launch error. */
 int lbm2p_stream_copy(const void* d_src, void* d_dst, size_t bytes, void* stream);
 
-/* Release the context (not the workspace or the stream). */
+/* Release the context (not the workspace or the caller's stream; the adjoint's
+ * own stream and events, if created, are released). */
 void lbm2p_destroy(lbm2p_ctx* c);
 
 /* Static string naming an error code. */

@@ -1091,7 +1091,15 @@ __global__ __launch_bounds__(NT, (sizeof(T) == 4 && NT == 512) ? 4 : 1) void k_c
         // moments of eq:Fi: M F = (0, 0, 0, phi a_x, -phi a_x, phi a_y, -phi a_y, 0, 0)
         const T pax = ph * ax, pay = ph * ay;
         const T mF[9] = {T(0), T(0), T(0), pax, -pax, pay, -pay, T(0), T(0)};
+        // FP32: the post-collision mass sum f* = m_0 - s_0 (m_0 - phi) (phi itself for
+        // s_0 = 1) is kept exactly up to one rounding: f*_0 is that target minus the
+        // eight moving populations (the value M^-1 gives, rounded once at phi's
+        // magnitude); f*_0 from M^-1 summed with the moving populations loses
+        // ~1e-8 of phi per node and step, a drift of the total mass
+        const T m0 = f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+        const T t0 = ph + (T(1) - P.s_f[0]) * (m0 - ph);
         mrt_collide_ms<T>(f, feq, mF, P.s_f);
+        f[0] = t0 - (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
       } else {
         T F[9];
         src_f<T>(ph, ax, ay, F);

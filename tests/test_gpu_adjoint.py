@@ -316,15 +316,13 @@ def test_c5_fp32_adjoint_against_fp64(nsteps):
     so that the comparison measures the FP32 adjoint, not a loss evaluated in
     FP32.
 
-    Bounds.  One step (the FP32 arithmetic of one reverse step): 1e-4 relative
-    for dL/dsigma and dL/dM, 1e-5 in relative L2 for dL/dphi0 (measured
-    2e-6, 2e-6, 7.5e-8).  4000 steps: 5e-2 for dL/dsigma and dL/dM (declared
-    before measuring; measured 2.2e-3 and 2.2e-3); dL/dphi0 declared 5e-2 in
-    L2, measured 0.125, bound set to 0.25: the field carried back 4000 steps
-    follows the FP32 trajectory, whose phi drifts from the FP64 one by 5e-5
-    (L2) at the end, and the gap grows with the horizon (1e-4 at 10 steps,
-    1e-2 at 500-1000, 2e-2 at 2000) while the scalar derivatives, integrals
-    over every node and step, stay within 2.2e-3."""
+    Bounds, declared before measuring.  One step (the FP32 arithmetic of one
+    reverse step): 1e-4 relative for dL/dsigma and dL/dM, 1e-5 in relative L2
+    for dL/dphi0 (measured 3.4e-7, 4.7e-8, 7.4e-8).  4000 steps: 5e-2 for
+    dL/dsigma, dL/dM and, in L2, dL/dphi0 (measured 6.8e-4, 3.4e-3, 1.0e-2).
+    The field carried back 4000 steps follows the FP32 trajectory; dL/dphi0
+    read 0.125 while the FP32 collision let the total mass drift (2.8e-4 per
+    step on the droplet), 1.0e-2 since it keeps it."""
     from paper_1812_02459_amd.binding import Sim
     wl = I.rising_bubble()
     rng = np.random.default_rng(0)
@@ -349,7 +347,7 @@ def test_c5_fp32_adjoint_against_fp64(nsteps):
     if nsteps == 1:
         assert rs <= 1e-4 and rm <= 1e-4 and rp <= 1e-5
     else:
-        assert rs <= 5e-2 and rm <= 5e-2 and rp <= 0.25
+        assert rs <= 5e-2 and rm <= 5e-2 and rp <= 5e-2
 
 
 def test_c5_fp32_adjoint_vs_central_differences():
@@ -360,10 +358,9 @@ def test_c5_fp32_adjoint_vs_central_differences():
     check the FP32 mode's gradients are meant for.  FP32 differences cannot
     resolve these derivatives (L changes by ~1e-12 relative), hence FP64 ones.
     Declared before the first run: 1e-2 relative for dL/dsigma and dL/dM, 5e-2
-    for dL/dphi0 . v.  Measured: 2.6e-3 and 7.5e-4 (met); dL/dphi0 . v 0.134,
-    MISSED (held here to 0.25): the phi0 field carried back 4000 steps follows
-    the FP32 trajectory (against the FP64 adjoint it is 0.125 off in L2), while
-    the FP64 adjoint meets the same difference to 1e-5."""
+    for dL/dphi0 . v.  Measured: 5.1e-3, 5.5e-3 and 3.4e-2 (dL/dphi0 . v read
+    0.13-0.17 while the FP32 collision let the total mass drift; the FP64
+    adjoint meets the same differences to 1e-5)."""
     from paper_1812_02459_amd.binding import Sim
     wl = I.rising_bubble()
     nsteps = 4000
@@ -398,4 +395,4 @@ def test_c5_fp32_adjoint_vs_central_differences():
         res[name] = (adj[name], fd, abs(adj[name] - fd) / abs(fd))
     print("C5 FP32 adjoint vs FP64 central differences, 4000 steps:",
           {k: "adj %.9e fd %.9e rel %.2e" % v_ for k, v_ in res.items()}, flush=True)
-    assert res["sigma"][2] <= 1e-2 and res["M"][2] <= 1e-2 and res["phi0.v"][2] <= 0.25
+    assert res["sigma"][2] <= 1e-2 and res["M"][2] <= 1e-2 and res["phi0.v"][2] <= 5e-2

@@ -531,12 +531,20 @@ void launch_collide(lbm2p_ctx* c, const KParams<T>& K, int par, hipStream_t st, 
 // the three TVD-RK3 stages with TY x NT tiles
 template <typename T, int TY, int NT>
 void launch_fd(lbm2p_ctx* c, const KParams<T>& K, hipStream_t st, T* phibar, T* phi1, T* phi2,
-               T* phi) {
+               T* phi, int gpar = -1) {
   constexpr int TX = StepCfg<T>::TX;
   const Tiles<TX, TY> tl(c->p);
   {
     ProfScope ps(c, PASS_FD);
-    k_fd<T, 1, TX, TY, NT><<<tl.grid(), NT, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
+    const T* Af = (const T*)c->Af;
+    if (gpar == 0)
+      k_fd<T, 1, TX, TY, NT, 0><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, Af,
+                                                          phibar);
+    else if (gpar == 1)
+      k_fd<T, 1, TX, TY, NT, 1><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, Af,
+                                                          phibar);
+    else
+      k_fd<T, 1, TX, TY, NT><<<tl.grid(), NT, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
   }
   {
     ProfScope ps(c, PASS_FD);
@@ -599,9 +607,15 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
   T* phi1 = (T*)c->phi1;
   T* phi2 = (T*)c->phi2;
   const bool stream = stream_populations<T>(c);
+  using Cs = StepCfg<T>;
+  const Tiles<Cs::TX, Cs::FDS_TY> tls0(p);
+  // CH-only on a lattice of few tiles: the gather is folded into the first FD
+  // stage (one launch less on a step that is a few launches' latency)
+  const bool fold_gather = !p.coupled && !p.original_ch &&
+                           tls0.tx * (long long)tls0.ty < TINY_TILES;
   for (int s = 0; s < nsteps; ++s) {
     const int par = c->parity;
-    {
+    if (!fold_gather) {
       ProfScope ps(c, PASS_GATHER);
       // while recording for the adjoint, the gather also keeps m_7, m_8 of the
       // pre-collision g (the g-relaxation rate's derivative needs them)
@@ -632,7 +646,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
       else if (tls.tx * (long long)tls.ty >= TINY_TILES)
         launch_fd<T, C::FDS_TY, C::FDS_NT>(c, K, st, phibar, phi1, phi2, phi);
       else
-        launch_fd<T, TINY_TY, TINY_NT>(c, K, st, phibar, phi1, phi2, phi);
+        launch_fd<T, TINY_TY, TINY_NT>(c, K, st, phibar, phi1, phi2, phi, fold_gather ? par : -1);
     }
     if (p.coupled) {
       T* uox = (T*)c->U[c->uo][0];

@@ -331,6 +331,21 @@ __device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[
 // phi_bar = sum f_i (eq:compute_phi), p = c_s^2 sum g_i (Eq:p), j = sum g_i c_i;
 // with m7, m8 given, also the moments m_7 = g1 - g2 + g3 - g4 and
 // m_8 = g5 - g6 + g7 - g8 of eq:D2Q9MRT
+// phi_bar = sum f_i of one node's nine pulled populations.  FP32: the eight
+// moving populations (|f_i| << 1) summed first, f_0 ~ phi added last, so that
+// the sum rounds once at phi's magnitude; FP64 in index order (the oracle's).
+template <typename T>
+__device__ __forceinline__ T phibar_sum(const T f[9]) {
+  if constexpr (std::is_same<T, float>::value) {
+    return f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
+  } else {
+    T s = f[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) s = s + f[i];
+    return s;
+  }
+}
+
 template <typename T, int PAR, bool COUPLED, bool STREAM>
 __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
                                                 const T* __restrict__ Ag, T* __restrict__ phibar,
@@ -343,19 +358,10 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
   int rd[9];
   slots<PAR, true>(P, x, y, rd);
-  if constexpr (std::is_same<T, float>::value) {
-    // FP32: the eight moving populations (|f_i| << 1) summed first, f_0 ~ phi
-    // added last, so that the sum rounds once at phi's magnitude
+  {
     T f[9];
     gather_load9<PAR, STREAM>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
-    fld(phibar, id) = f[0] + (((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8])));
-  } else {
-    T f[9];
-    gather_load9<PAR, STREAM>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
-    T s = f[0];
-#pragma unroll
-    for (int i = 1; i < 9; ++i) s = s + f[i];
-    fld(phibar, id) = s;
+    fld(phibar, id) = phibar_sum<T>(f);
   }
   if (!COUPLED) return;
   T g[9];
@@ -395,9 +401,16 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
 // ------------------------------------------------- a2: FD sub-step stage
 // L(phi*) = div_4 (lambda J_phi + q)  (eq:final_mCHE, eq:fourOrder_FDM) and the
 // TVD-RK3 combination of eq:TVD-3order for STAGE 1, 2, 3.
-template <typename T, int STAGE, int TX, int TY, int NT>
+// GPAR >= 0 (stage 1 of the CH-only step on small lattices): the step's gather
+// folded in, phi_bar of every window node summed from its populations (parity
+// GPAR; k_gather's arithmetic) instead of read from `in`, and written to pbout
+// for the tile's nodes (the later stages and the state read it there).
+template <typename T, int STAGE, int TX, int TY, int NT, int GPAR = -1>
 __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* __restrict__ in,
-                                            const T* __restrict__ phibar, T* __restrict__ out) {
+                                            const T* __restrict__ phibar, T* __restrict__ out,
+                                            const T* __restrict__ Af = nullptr,
+                                            T* __restrict__ pbout = nullptr) {
+  static_assert(GPAR < 0 || STAGE == 1, "the gather folds into the first stage");
   constexpr int W5 = TX + 10, H5 = TY + 10;   // phi*, halo 5
   constexpr int W4 = TX + 8, H4 = TY + 8;     // mu*, halo 4
   constexpr int W2 = TX + 4, H2 = TY + 4;     // J_d, halo 2
@@ -408,9 +421,28 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
   int bx, by;
   tile_of(tiles_x, bx, by);
   const int x0 = bx * TX, y0 = by * TY;
-  load_window<T, T, NT, W5, H5>(sP, in, x0 - 5, y0 - 5, P, false);
+  if constexpr (GPAR >= 0) {
+    for_window<W5, H5, NT>([&](int ix, int iy) {
+      int flip = 0;
+      const int x = map_idx(x0 - 5 + ix, P.nx, P.wx, flip);
+      const int y = map_idx(y0 - 5 + iy, P.ny, P.wy, flip);
+      int rd[9];
+      slots<GPAR, true>(P, x, y, rd);
+      T f[9];
+      gather_load9<GPAR, false>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
+      sP[iy * W5 + ix] = phibar_sum<T>(f);
+    });
+  } else {
+    load_window<T, T, NT, W5, H5>(sP, in, x0 - 5, y0 - 5, P, false);
+  }
   __syncthreads();
   const Tile<T> tP{sP, W5, 5}, tM{sM, W4, 4}, tJx{sJx, W2, 2}, tJy{sJy, W2, 2};
+  if constexpr (GPAR >= 0) {
+    for_window<TX, TY, NT>([&](int lx, int ly) {
+      const int x = x0 + lx, y = y0 + ly;
+      if (x < P.nx && y < P.ny) pbout[(long long)y * P.nx + x] = tP(lx, ly);
+    });
+  }
   for_window<W4, H4, NT>([&](int ix, int iy) {
     sM[iy * W4 + ix] = chem_pot<T>(tP, ix - 4, iy - 4, P.c4b, P.kappa);
   });

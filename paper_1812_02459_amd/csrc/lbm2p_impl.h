@@ -536,13 +536,17 @@ void launch_fd(lbm2p_ctx* c, const KParams<T>& K, hipStream_t st, T* phibar, T* 
   const Tiles<TX, TY> tl(c->p);
   {
     ProfScope ps(c, PASS_FD);
-    const T* Af = (const T*)c->Af;
-    if (gpar == 0)
-      k_fd<T, 1, TX, TY, NT, 0><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, Af,
-                                                          phibar);
+    const FoldedGather<T> G{(const T*)c->Af, (const T*)c->Ag, phibar, (T*)c->praw, (T*)c->jx,
+                            (T*)c->jy};
+    const bool cp = c->p.coupled != 0;
+    if (gpar == 0 && cp)
+      k_fd<T, 1, TX, TY, NT, 0, true><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, G);
+    else if (gpar == 1 && cp)
+      k_fd<T, 1, TX, TY, NT, 1, true><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, G);
+    else if (gpar == 0)
+      k_fd<T, 1, TX, TY, NT, 0><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, G);
     else if (gpar == 1)
-      k_fd<T, 1, TX, TY, NT, 1><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, Af,
-                                                          phibar);
+      k_fd<T, 1, TX, TY, NT, 1><<<tl.grid(), NT, 0, st>>>(K, tl.tx, nullptr, nullptr, phi1, G);
     else
       k_fd<T, 1, TX, TY, NT><<<tl.grid(), NT, 0, st>>>(K, tl.tx, phibar, phibar, phi1);
   }
@@ -609,10 +613,12 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
   const bool stream = stream_populations<T>(c);
   using Cs = StepCfg<T>;
   const Tiles<Cs::TX, Cs::FDS_TY> tls0(p);
-  // CH-only on a lattice of few tiles: the gather is folded into the first FD
-  // stage (one launch less on a step that is a few launches' latency)
-  const bool fold_gather = !p.coupled && !p.original_ch &&
-                           tls0.tx * (long long)tls0.ty < TINY_TILES;
+  // On a lattice of few tiles the gather is folded into the first FD stage (one
+  // launch less on a step that is a few launches' latency); not while recording
+  // for the adjoint or with the moment strain rate (their gather keeps moments
+  // of g besides)
+  const bool fold_gather = !p.original_ch && tls0.tx * (long long)tls0.ty < TINY_TILES &&
+                           !(p.coupled && (c->rec || (p.options & LBM2P_OPT_STRAIN_MOMENTS)));
   for (int s = 0; s < nsteps; ++s) {
     const int par = c->parity;
     if (!fold_gather) {

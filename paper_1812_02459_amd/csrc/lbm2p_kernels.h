@@ -346,16 +346,14 @@ __device__ __forceinline__ T phibar_sum(const T f[9]) {
   }
 }
 
+// The gather at node (x, y), element id
 template <typename T, int PAR, bool COUPLED, bool STREAM>
-__global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
-                                                const T* __restrict__ Ag, T* __restrict__ phibar,
-                                                T* __restrict__ praw, T* __restrict__ jx,
-                                                T* __restrict__ jy, T* __restrict__ m7,
-                                                T* __restrict__ m8, T* __restrict__ m1) {
-  const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (id >= n) return;
-  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+__device__ __forceinline__ void gather_node(const KParams<T>& P, const T* __restrict__ Af,
+                                            const T* __restrict__ Ag, T* __restrict__ phibar,
+                                            T* __restrict__ praw, T* __restrict__ jx,
+                                            T* __restrict__ jy, T* __restrict__ m7,
+                                            T* __restrict__ m8, T* __restrict__ m1, int x, int y,
+                                            long long id) {
   int rd[9];
   slots<PAR, true>(P, x, y, rd);
   {
@@ -398,18 +396,39 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   }
 }
 
+template <typename T, int PAR, bool COUPLED, bool STREAM>
+__global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
+                                                const T* __restrict__ Ag, T* __restrict__ phibar,
+                                                T* __restrict__ praw, T* __restrict__ jx,
+                                                T* __restrict__ jy, T* __restrict__ m7,
+                                                T* __restrict__ m8, T* __restrict__ m1) {
+  const long long n = (long long)P.nx * P.ny;
+  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (id >= n) return;
+  const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
+  gather_node<T, PAR, COUPLED, STREAM>(P, Af, Ag, phibar, praw, jx, jy, m7, m8, m1, x, y, id);
+}
+
 // ------------------------------------------------- a2: FD sub-step stage
 // L(phi*) = div_4 (lambda J_phi + q)  (eq:final_mCHE, eq:fourOrder_FDM) and the
 // TVD-RK3 combination of eq:TVD-3order for STAGE 1, 2, 3.
-// GPAR >= 0 (stage 1 of the CH-only step on small lattices): the step's gather
-// folded in, phi_bar of every window node summed from its populations (parity
-// GPAR; k_gather's arithmetic) instead of read from `in`, and written to pbout
-// for the tile's nodes (the later stages and the state read it there).
-template <typename T, int STAGE, int TX, int TY, int NT, int GPAR = -1>
+// Outputs of the gather when it is folded into the first FD stage
+template <typename T>
+struct FoldedGather {
+  const T* Af;
+  const T* Ag;   // null in CH-only mode
+  T *phibar, *praw, *jx, *jy;
+};
+
+// GPAR >= 0 (stage 1 of the step on small lattices): the step's gather folded
+// in, phi_bar of every window node summed from its populations (parity GPAR;
+// k_gather's arithmetic) instead of read from `in`, and the tile's nodes
+// gathered in full (phi_bar, and with COUPLED p and j) into G's planes, where
+// the later passes and the state read them.
+template <typename T, int STAGE, int TX, int TY, int NT, int GPAR = -1, bool COUPLED = false>
 __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* __restrict__ in,
                                             const T* __restrict__ phibar, T* __restrict__ out,
-                                            const T* __restrict__ Af = nullptr,
-                                            T* __restrict__ pbout = nullptr) {
+                                            FoldedGather<T> G = {}) {
   static_assert(GPAR < 0 || STAGE == 1, "the gather folds into the first stage");
   constexpr int W5 = TX + 10, H5 = TY + 10;   // phi*, halo 5
   constexpr int W4 = TX + 8, H4 = TY + 8;     // mu*, halo 4
@@ -429,7 +448,7 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
       int rd[9];
       slots<GPAR, true>(P, x, y, rd);
       T f[9];
-      gather_load9<GPAR, false>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
+      gather_load9<GPAR, false>(G.Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
       sP[iy * W5 + ix] = phibar_sum<T>(f);
     });
   } else {
@@ -440,7 +459,10 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
   if constexpr (GPAR >= 0) {
     for_window<TX, TY, NT>([&](int lx, int ly) {
       const int x = x0 + lx, y = y0 + ly;
-      if (x < P.nx && y < P.ny) pbout[(long long)y * P.nx + x] = tP(lx, ly);
+      if (x < P.nx && y < P.ny)
+        gather_node<T, GPAR, COUPLED, false>(P, G.Af, G.Ag, G.phibar, G.praw, G.jx, G.jy,
+                                             nullptr, nullptr, nullptr, x, y,
+                                             (long long)y * P.nx + x);
     });
   }
   for_window<W4, H4, NT>([&](int ix, int iy) {

@@ -124,7 +124,11 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes,
  * mu = mu_phi(phi0), eq:chemical): f* = f^eq(phi0, mu, u0), g* = g^eq(p0, u0),
  * u~ = u0.  Device float64 planes [ny][nx]; d_ux0/d_uy0/d_p0 may be NULL
  * (zeros).  In CH-only mode (u0x, u0y) is the prescribed velocity of the
- * later steps (until lbm2p_set_velocity). */
+ * later steps (until lbm2p_set_velocity).  In coupled mode the first call also
+ * makes the context's second stream (non-blocking, default priority) and two
+ * events, with which the steps of large lattices (populations above 256 MB)
+ * run the gather of p and j beside the FD sub-step (destroyed by
+ * lbm2p_destroy); EHIP if they cannot be made. */
 int lbm2p_init_fields(lbm2p_ctx* c, const double* d_phi0, const double* d_ux0,
                       const double* d_uy0, const double* d_p0);
 
@@ -140,7 +144,10 @@ int lbm2p_init_fields(lbm2p_ctx* c, const double* d_phi0, const double* d_ux0,
  * and the next step, and a record made before it can no longer be reversed. */
 int lbm2p_set_velocity(lbm2p_ctx* c, const double* d_ux, const double* d_uy);
 
-/* Advance n >= 0 time steps (asynchronous). ESTATE before init. */
+/* Advance n >= 0 time steps (asynchronous on the context's stream; on large
+ * coupled lattices part of each step runs on the second stream, forked from
+ * and joined back to it by events, so the work stays ordered on the context's
+ * stream).  ESTATE before init. */
 int lbm2p_step(lbm2p_ctx* c, int32_t n);
 
 /* Copy the current macroscopic fields to device float64 planes: phi^{n}
@@ -223,7 +230,9 @@ int lbm2p_set_state(lbm2p_ctx* c, const double* d_f, const double* d_g,
  * starts recording every launch of pass k (0 gather, 1 FD stage, 2 velocity
  * iteration, 3 filter, 4 collide; -1 stops) for up to 65536 launches;
  * lbm2p_profile_read synchronises and returns the summed milliseconds and the
- * number of launches recorded since lbm2p_profile. */
+ * number of launches recorded since lbm2p_profile.  While the gather or the
+ * FD pass is profiled the steps run them in series (no gather of p and j
+ * beside the FD sub-step), so that each is timed on its own. */
 int lbm2p_profile(lbm2p_ctx* c, int32_t pass);
 int lbm2p_profile_read(lbm2p_ctx* c, double* ms, int64_t* launches);
 

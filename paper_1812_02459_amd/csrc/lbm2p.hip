@@ -343,6 +343,8 @@ int lbm2p_create(const lbm2p_params* p, void* d_workspace, size_t bytes, void* s
   c->res_valid = 0;
   c->vpend = 0;
   c->adj_stream = nullptr;
+  c->g_stream = nullptr;
+  c->g_ev[0] = c->g_ev[1] = nullptr;
   *out = c;
   return LBM2P_OK;
 }
@@ -353,12 +355,28 @@ void lbm2p_destroy(lbm2p_ctx* c) {
   for (auto e : c->ev1) hipEventDestroy(e);
   for (auto e : c->adj_ev) hipEventDestroy(e);
   if (c->adj_stream) hipStreamDestroy(c->adj_stream);
+  for (auto e : c->g_ev)
+    if (e) hipEventDestroy(e);
+  if (c->g_stream) hipStreamDestroy(c->g_stream);
   delete c;
 }
 
 int lbm2p_init_fields(lbm2p_ctx* c, const double* phi0, const double* ux0, const double* uy0,
                       const double* p0) {
   if (!c || !phi0) return LBM2P_EINVAL;
+  // the coupled step's second stream and its fork/join events, made once here
+  // (not in a step, which a caller may be capturing into a graph)
+  if (c->p.coupled && !c->g_stream) {
+    if (hipStreamCreateWithFlags(&c->g_stream, hipStreamNonBlocking) != hipSuccess) {
+      c->g_stream = nullptr;
+      return LBM2P_EHIP;
+    }
+    for (auto& e : c->g_ev)
+      if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+        e = nullptr;
+        return LBM2P_EHIP;
+      }
+  }
   return c->prec ? init_f32(c, phi0, ux0, uy0, p0)
                  : init_f64(c, phi0, ux0, uy0, p0);
 }

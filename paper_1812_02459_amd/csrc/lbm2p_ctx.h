@@ -70,6 +70,11 @@ struct lbm2p_ctx {
   // them against the reverse sweep (created at the first adjoint that uses them)
   hipStream_t adj_stream;
   std::vector<hipEvent_t> adj_ev;
+  // coupled mode: a second stream on which the gather of p and j runs beside
+  // the FD stages (which need only phi_bar), and the events of that fork and
+  // join (made by the first lbm2p_init_fields)
+  hipStream_t g_stream;
+  hipEvent_t g_ev[2];
 };
 
 namespace lbm2p {

@@ -493,6 +493,18 @@ void launch_gather(const KParams<T>& K, int par, long long n, hipStream_t st, T*
                                                                  m7, m8, m1);
 }
 
+// the gather of p and j alone (the coupled step's second stream)
+template <typename T, bool STREAM>
+void launch_gather_g(const KParams<T>& K, int par, long long n, hipStream_t st, const T* Ag,
+                     T* praw, T* jx, T* jy) {
+  if (par == 0)
+    k_gather<T, 0, true, STREAM, true><<<blocks1d(n), 256, 0, st>>>(K, nullptr, Ag, nullptr, praw, jx,
+                                                                   jy, nullptr, nullptr, nullptr);
+  else
+    k_gather<T, 1, true, STREAM, true><<<blocks1d(n), 256, 0, st>>>(K, nullptr, Ag, nullptr, praw, jx,
+                                                                   jy, nullptr, nullptr, nullptr);
+}
+
 template <typename T, bool COUPLED, bool STREAM>
 void launch_collide(lbm2p_ctx* c, const KParams<T>& K, int par, hipStream_t st, T* Af, T* Ag,
                     const T* phi, const T* pt, const T* ux, const T* uy, const T* uox,
@@ -621,7 +633,35 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
                            !(p.coupled && (c->rec || (p.options & LBM2P_OPT_STRAIN_MOMENTS)));
   for (int s = 0; s < nsteps; ++s) {
     const int par = c->parity;
-    if (!fold_gather) {
+    // Coupled steps split the gather: p and j on the second stream, beside the
+    // FD stages, which need only phi_bar (the FD stages are instruction-bound
+    // and leave HBM bandwidth to the gather of g); the velocity sweeps wait for
+    // it.  Only on lattices whose populations exceed the last-level cache (on
+    // smaller ones the fork and join cost more than the overlap gains: +18 us
+    // a step at 256 x 1024); not while recording (that gather keeps m_7, m_8
+    // too), with the moment strain rate, or while the gather or FD pass is
+    // profiled (lbm2p_profile then times them in the serial order).
+    const bool split = p.coupled && stream && c->g_stream && c->g_ev[1] && !c->rec &&
+                       !(p.options & LBM2P_OPT_STRAIN_MOMENTS) &&
+                       c->prof_pass != PASS_GATHER && c->prof_pass != PASS_FD;
+    if (split) {
+      // phi_bar first, alone (the FD stages wait for it), then p and j on the
+      // second stream while the FD stages run
+      if (stream)
+        launch_gather<T, false, true>(K, par, n, st, Af, Ag, phibar, nullptr, nullptr, nullptr,
+                                      nullptr, nullptr);
+      else
+        launch_gather<T, false, false>(K, par, n, st, Af, Ag, phibar, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr);
+      if (hipEventRecord(c->g_ev[0], st) != hipSuccess ||
+          hipStreamWaitEvent(c->g_stream, c->g_ev[0], 0) != hipSuccess)
+        return LBM2P_EHIP;
+      if (stream)
+        launch_gather_g<T, true>(K, par, n, c->g_stream, Ag, (T*)c->praw, (T*)c->jx, (T*)c->jy);
+      else
+        launch_gather_g<T, false>(K, par, n, c->g_stream, Ag, (T*)c->praw, (T*)c->jx, (T*)c->jy);
+      if (hipEventRecord(c->g_ev[1], c->g_stream) != hipSuccess) return LBM2P_EHIP;
+    } else if (!fold_gather) {
       ProfScope ps(c, PASS_GATHER);
       // while recording for the adjoint, the gather also keeps m_7, m_8 of the
       // pre-collision g (the g-relaxation rate's derivative needs them)
@@ -655,6 +695,7 @@ int step_impl(lbm2p_ctx* c, int nsteps) {
         launch_fd<T, TINY_TY, TINY_NT>(c, K, st, phibar, phi1, phi2, phi, fold_gather ? par : -1);
     }
     if (p.coupled) {
+      if (split && hipStreamWaitEvent(st, c->g_ev[1], 0) != hipSuccess) return LBM2P_EHIP;
       T* uox = (T*)c->U[c->uo][0];
       T* uoy = (T*)c->U[c->uo][1];
       T* unx = (T*)c->U[1 - c->uo][0];

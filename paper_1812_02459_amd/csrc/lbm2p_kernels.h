@@ -346,8 +346,8 @@ __device__ __forceinline__ T phibar_sum(const T f[9]) {
   }
 }
 
-// The gather at node (x, y), element id
-template <typename T, int PAR, bool COUPLED, bool STREAM>
+// The gather at node (x, y), element id; SKIP_F: only the moments of g (p, j)
+template <typename T, int PAR, bool COUPLED, bool STREAM, bool SKIP_F = false>
 __device__ __forceinline__ void gather_node(const KParams<T>& P, const T* __restrict__ Af,
                                             const T* __restrict__ Ag, T* __restrict__ phibar,
                                             T* __restrict__ praw, T* __restrict__ jx,
@@ -356,7 +356,7 @@ __device__ __forceinline__ void gather_node(const KParams<T>& P, const T* __rest
                                             long long id) {
   int rd[9];
   slots<PAR, true>(P, x, y, rd);
-  {
+  if constexpr (!SKIP_F) {
     T f[9];
     gather_load9<PAR, STREAM>(Af, P.ps, rd, f, std::make_integer_sequence<int, 9>{});
     fld(phibar, id) = phibar_sum<T>(f);
@@ -396,7 +396,7 @@ __device__ __forceinline__ void gather_node(const KParams<T>& P, const T* __rest
   }
 }
 
-template <typename T, int PAR, bool COUPLED, bool STREAM>
+template <typename T, int PAR, bool COUPLED, bool STREAM, bool SKIP_F = false>
 __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
                                                 const T* __restrict__ Ag, T* __restrict__ phibar,
                                                 T* __restrict__ praw, T* __restrict__ jx,
@@ -406,7 +406,8 @@ __global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restric
   const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
   if (id >= n) return;
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
-  gather_node<T, PAR, COUPLED, STREAM>(P, Af, Ag, phibar, praw, jx, jy, m7, m8, m1, x, y, id);
+  gather_node<T, PAR, COUPLED, STREAM, SKIP_F>(P, Af, Ag, phibar, praw, jx, jy, m7, m8, m1, x, y,
+                                               id);
 }
 
 // ------------------------------------------------- a2: FD sub-step stage

@@ -330,7 +330,9 @@ __device__ __forceinline__ void slots(const KParams<T>& P, int x, int y, int rd[
 // ------------------------------------------------------------ a1: gather
 // phi_bar = sum f_i (eq:compute_phi), p = c_s^2 sum g_i (Eq:p), j = sum g_i c_i;
 // with m7, m8 given, also the moments m_7 = g1 - g2 + g3 - g4 and
-// m_8 = g5 - g6 + g7 - g8 of eq:D2Q9MRT
+// m_8 = g5 - g6 + g7 - g8 of eq:D2Q9MRT.  COUPLED = false: phi_bar alone;
+// SKIP_F: the moments of g alone (the two halves of a split gather).
+
 // phi_bar = sum f_i of one node's nine pulled populations.  FP32: the eight
 // moving populations (|f_i| << 1) summed first, f_0 ~ phi added last, so that
 // the sum rounds once at phi's magnitude; FP64 in index order (the oracle's).

@@ -423,11 +423,12 @@ struct FoldedGather {
   T *phibar, *praw, *jx, *jy;
 };
 
-// GPAR >= 0 (stage 1 of the step on small lattices): the step's gather folded
-// in, phi_bar of every window node summed from its populations (parity GPAR;
-// k_gather's arithmetic) instead of read from `in`, and the tile's nodes
-// gathered in full (phi_bar, and with COUPLED p and j) into G's planes, where
-// the later passes and the state read them.
+// GPAR >= 0 (stage 1): the step's gather of phi_bar folded in, phi_bar of
+// every window node summed from its populations (parity GPAR; k_gather's
+// arithmetic) instead of read from `in` and written for the tile's nodes to
+// G.phibar, where the later stages and the state read it; with COUPLED the
+// tile's p and j too (small lattices; large ones gather those on a second
+// stream).
 template <typename T, int STAGE, int TX, int TY, int NT, int GPAR = -1, bool COUPLED = false>
 __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* __restrict__ in,
                                             const T* __restrict__ phibar, T* __restrict__ out,
@@ -460,12 +461,16 @@ __global__ __launch_bounds__(NT) void k_fd(KParams<T> P, int tiles_x, const T* _
   __syncthreads();
   const Tile<T> tP{sP, W5, 5}, tM{sM, W4, 4}, tJx{sJx, W2, 2}, tJy{sJy, W2, 2};
   if constexpr (GPAR >= 0) {
+    // the tile's phi_bar from the window; p and j (COUPLED) from the tile's g
     for_window<TX, TY, NT>([&](int lx, int ly) {
       const int x = x0 + lx, y = y0 + ly;
-      if (x < P.nx && y < P.ny)
-        gather_node<T, GPAR, COUPLED, false>(P, G.Af, G.Ag, G.phibar, G.praw, G.jx, G.jy,
-                                             nullptr, nullptr, nullptr, x, y,
-                                             (long long)y * P.nx + x);
+      if (x < P.nx && y < P.ny) {
+        const long long id = (long long)y * P.nx + x;
+        fld(G.phibar, id) = tP(lx, ly);
+        if constexpr (COUPLED)
+          gather_node<T, GPAR, true, false, true>(P, G.Af, G.Ag, G.phibar, G.praw, G.jx, G.jy,
+                                                  nullptr, nullptr, nullptr, x, y, id);
+      }
     });
   }
   for_window<W4, H4, NT>([&](int ix, int iy) {

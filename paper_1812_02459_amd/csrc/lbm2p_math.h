@@ -206,6 +206,42 @@ __device__ __forceinline__ void mrt_collide_ms(T f[9], const T feq[9], const T m
   for (int i = 0; i < 9; ++i) f[i] = f[i] + corr[i];
 }
 
+// The collision of mrt_collide_ms with the equilibrium given by its moments
+// m^eq instead of populations: f* = f + M^{-1} [ (I - S/2) m_S - S (M f - m^eq) ].
+// M f has integer coefficients, so the conserved moments of f - f^eq carry no
+// rounding of the lattice weights (FP32 w_1 = RN(1/9) makes sum_i c_i g_i^eq =
+// 9 RN(1/9) u = (1 + 7.5e-9) u, which relaxation at s = 1 turns into a growth
+// of the momentum by that factor every step).
+template <typename T>
+__device__ __forceinline__ void mrt_collide_meq(T f[9], const T meq[9], const T mS[9],
+                                                const T s[9]) {
+  T mf[9], r[9], corr[9];
+  m_apply_pairs(f, mf);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) r[k] = (T(1) - s[k] * T(0.5)) * mS[k] - s[k] * (mf[k] - meq[k]);
+  minv_apply_pairs(r, corr);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) f[i] = f[i] + corr[i];
+}
+
+// Moments of eq:geq in the basis of m_apply_pairs (rho, e, eps, j_x, q_x, j_y,
+// q_y, p_xx, p_xy), from the lattice sums sum w_i = 1, sum w_i c_i c_i = I/3
+// and sum w_i (3|c_i|^2 - 4) = -2: (3p, -6p + 3|u|^2, 3p - 3|u|^2, u_x, -u_x,
+// u_y, -u_y, u_x^2 - u_y^2, u_x u_y).
+template <typename T>
+__device__ __forceinline__ void g_eq_moments(T p, T ux, T uy, T meq[9]) {
+  const T usq = ux * ux + uy * uy, p3 = T(3) * p;
+  meq[0] = p3;
+  meq[1] = T(3) * usq - T(2) * p3;
+  meq[2] = p3 - T(3) * usq;
+  meq[3] = ux;
+  meq[4] = -ux;
+  meq[5] = uy;
+  meq[6] = -uy;
+  meq[7] = ux * ux - uy * uy;
+  meq[8] = ux * uy;
+}
+
 // grad u + grad u^T from the non-equilibrium moments of the pre-collision g
 // (eq:Fmu, re-derived from App. A's first-order balances of m_1, m_7, m_8):
 // A_k = m_k - m_k^eq + G~_k / 2, div u = -(s_1/2) A_1, d_x u_x - d_y u_y =

@@ -319,10 +319,10 @@ def test_c5_fp32_adjoint_against_fp64(nsteps):
     Bounds, declared before measuring.  One step (the FP32 arithmetic of one
     reverse step): 1e-4 relative for dL/dsigma and dL/dM, 1e-5 in relative L2
     for dL/dphi0 (measured 3.4e-7, 4.7e-8, 7.4e-8).  4000 steps: 5e-2 for
-    dL/dsigma, dL/dM and, in L2, dL/dphi0 (measured 6.8e-4, 3.4e-3, 1.0e-2).
+    dL/dsigma, dL/dM and, in L2, dL/dphi0 (measured 6.7e-4, 3.1e-3, 2.4e-2).
     The field carried back 4000 steps follows the FP32 trajectory; dL/dphi0
     read 0.125 while the FP32 collision let the total mass drift (2.8e-4 per
-    step on the droplet), 1.0e-2 since it keeps it."""
+    step on the droplet), 1.0e-2 to 2.4e-2 since it keeps it."""
     from paper_1812_02459_amd.binding import Sim
     wl = I.rising_bubble()
     rng = np.random.default_rng(0)
@@ -358,7 +358,7 @@ def test_c5_fp32_adjoint_vs_central_differences():
     check the FP32 mode's gradients are meant for.  FP32 differences cannot
     resolve these derivatives (L changes by ~1e-12 relative), hence FP64 ones.
     Declared before the first run: 1e-2 relative for dL/dsigma and dL/dM, 5e-2
-    for dL/dphi0 . v.  Measured: 5.1e-3, 5.5e-3 and 3.4e-2 (dL/dphi0 . v read
+    for dL/dphi0 . v.  Measured: 5.4e-3, 4.5e-3 and 3.8e-2 (dL/dphi0 . v read
     0.13-0.17 while the FP32 collision let the total mass drift; the FP64
     adjoint meets the same differences to 1e-5)."""
     from paper_1812_02459_amd.binding import Sim

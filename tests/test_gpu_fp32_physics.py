@@ -136,11 +136,14 @@ def test_fp32_deviation_storage_with_background_pressure():
     (6e-8 relative) swamps the O(1e-3) velocity part; with p_ref = p0 the
     stored values are the O(1e-3) deviations.  Declared: with the shift the
     FP32 velocity within 1e-5 (relative L2) of the FP64 one after 2000 steps,
-    and at least 10 times closer than without it; measured 2.7e-5 against
-    4.6e-3 plain, so the first bar is relaxed to 1e-4: what remains is the FP32
-    storage of p~ ~ 0.5 itself (ulp 6e-8), whose gradient enters the forcing
-    b = F/rho - grad p~.  The shift is transparent in FP64 (the same run with
-    and without it agrees to 1e-12; measured 4e-13)."""
+    and at least 10 times closer than without it.  First measured 2.7e-5
+    against 4.6e-3 plain, the same 2.9e-5 with p0 = 0: an amplitude bias
+    growing linearly in time, from two FP32 roundings of constants that
+    compound every step (the momentum of g^eq, 9 RN(1/9) u = (1 + 7.5e-9) u,
+    relaxed at s = 1; the SF-11 coefficients' FP32 sum, -4.7e-9).  With the
+    equilibrium taken by its moments and the filter in difference form:
+    3.7e-6 against 9.7e-5 plain.  The shift is transparent in FP64 (the same
+    run with and without it agrees to 1e-12; measured 4e-13)."""
     from paper_1812_02459_amd.binding import Sim
     n, steps = 128, 2000
     y = np.arange(n, dtype=np.float64)[:, None] * np.ones((1, n))
@@ -166,7 +169,7 @@ def test_fp32_deviation_storage_with_background_pressure():
     _record("deviation_storage", dict(fp64_shift_vs_plain=d64, fp32_err_shifted=e_shift,
                                       fp32_err_plain=e_plain))
     assert d64 <= 1e-12, d64
-    assert e_shift <= 1e-4, e_shift
+    assert e_shift <= 1e-5, e_shift
     assert e_shift * 10 <= e_plain, (e_shift, e_plain)
 
 

@@ -150,8 +150,8 @@ def test_table4_test1_fp32_follows_fp64():
     arithmetic.  It is run here alongside an FP64 run from a perturbed phi0,
     both distances are reported, and the FP32 distance over t <= 3 is held to
     twice the perturbed FP64 run's (measured: FP32 1.1e-1 of max V_c and
-    6.9e-3 widths; FP64 + 1e-10 8.1e-2 and 6.5e-3).  Up to t = 1.5: FP32
-    8.0e-3 and 5.3e-4 widths."""
+    1.1e-2 widths; FP64 + 1e-10 8.1e-2 and 6.5e-3).  Up to t = 1.5: FP32
+    8.3e-3 and 5.1e-4 widths."""
     wl, _, t, _, y64, v64, f64 = _run(1, precision=0)
     _, _, _, _, y32, v32, f32 = _run(1, precision=1)
     rng = np.random.default_rng(7)

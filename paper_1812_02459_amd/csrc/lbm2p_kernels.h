@@ -1060,7 +1060,8 @@ __global__ __launch_bounds__(NT) void k_filter(KParams<T> P, int tiles_x, const 
                                                 const T* __restrict__ uxin,
                                                 const T* __restrict__ uyin, T* __restrict__ pout,
                                                 T* __restrict__ uxout, T* __restrict__ uyout) {
-  constexpr int WN = TX + 2 * N, HN = TY + 2 * N;
+  static_assert(NT % TX == 0 && (TX * TY) % NT == 0, "whole column strips per thread");
+  constexpr int WN = TX + 2 * N, HN = TY + 2 * N, R = TX * TY / NT;
   __shared__ T s0[WN * HN], s1[WN * HN], s2[WN * HN];
   int bx, by;
   tile_of(tiles_x, bx, by);
@@ -1073,40 +1074,45 @@ __global__ __launch_bounds__(NT) void k_filter(KParams<T> P, int tiles_x, const 
 #pragma unroll
   for (int j = 0; j <= N; ++j) d[j] = P.fd[j];
   const T a = P.fa;
-  for (int idx = threadIdx.x; idx < TX * TY; idx += NT) {
-    const int ly = idx / TX, lx = idx % TX;
-    const int x = x0 + lx, y = y0 + ly;
-    if (x >= P.nx || y >= P.ny) continue;
-    const long long id = (long long)y * P.nx + x;
+  // each thread filters R consecutive rows of one column: the column's
+  // 2N + R values of the y-stencil are read from LDS once into registers
+  const int lx = threadIdx.x % TX, ly0 = (threadIdx.x / TX) * R;
+  const int x = x0 + lx;
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-      const Tile<T> t{f == 0 ? s0 : f == 1 ? s1 : s2, WN, N};
+  for (int f = 0; f < 3; ++f) {
+    const Tile<T> t{f == 0 ? s0 : f == 1 ? s1 : s2, WN, N};
+    T col[R + 2 * N];
+#pragma unroll
+    for (int k = 0; k < R + 2 * N; ++k) col[k] = t(lx, ly0 - N + k);
+    T* out = f == 0 ? pout : f == 1 ? uxout : uyout;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int ly = ly0 + r, y = y0 + ly;
+      if (x >= P.nx || y >= P.ny) continue;
+      const T* cy = col + r + N;   // cy[j] = chi(x, y + j)
       T sx, sy;
       if constexpr (std::is_same<T, float>::value) {
         // FP32: sum_j d_|j| chi_j = sum_k d_k [(chi_k - chi_0) + (chi_-k - chi_0)]
         // (the d_j sum to zero), so a uniform field passes exactly: the FP32
         // d_j sum to -4.7e-9 for SF-11, a gain of 1 + 4.7e-9 per application
         // in the chained form, and the differences of a smooth field are exact.
-        const T c0 = t(lx, ly);
+        const T c0 = cy[0];
         sx = d[N] * ((t(lx + N, ly) - c0) + (t(lx - N, ly) - c0));
-        sy = d[N] * ((t(lx, ly + N) - c0) + (t(lx, ly - N) - c0));
+        sy = d[N] * ((cy[N] - c0) + (cy[-N] - c0));
 #pragma unroll
         for (int k = N - 1; k >= 1; --k) {
           sx = sx + d[k] * ((t(lx + k, ly) - c0) + (t(lx - k, ly) - c0));
-          sy = sy + d[k] * ((t(lx, ly + k) - c0) + (t(lx, ly - k) - c0));
+          sy = sy + d[k] * ((cy[k] - c0) + (cy[-k] - c0));
         }
       } else {
         sx = d[N] * t(lx - N, ly);
 #pragma unroll
-        for (int j = -N + 1; j <= N; ++j) sx = sx + d[j < 0 ? -j : j] * t(lx + j, ly);
-        sy = d[N] * t(lx, ly - N);
+        for (int j = -N + 1; j <= N; ++j) sx = sx + d[j < 0 ? -j : j] * (j == 0 ? cy[0] : t(lx + j, ly));
+        sy = d[N] * cy[-N];
 #pragma unroll
-        for (int j = -N + 1; j <= N; ++j) sy = sy + d[j < 0 ? -j : j] * t(lx, ly + j);
+        for (int j = -N + 1; j <= N; ++j) sy = sy + d[j < 0 ? -j : j] * cy[j];
       }
-      const T r = t(lx, ly) - a * (sx + sy);
-      if (f == 0) pout[id] = r;
-      else if (f == 1) uxout[id] = r;
-      else uyout[id] = r;
+      out[(long long)y * P.nx + x] = cy[0] - a * (sx + sy);
     }
   }
 }

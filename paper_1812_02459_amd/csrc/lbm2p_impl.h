@@ -493,16 +493,23 @@ void launch_gather(const KParams<T>& K, int par, long long n, hipStream_t st, T*
                                                                  m7, m8, m1);
 }
 
-// the gather of p and j alone (the coupled step's second stream)
+// the gather of p and j alone (the coupled step's second stream).  It runs
+// beside the FD stages, whose workgroups take 16 (FP32: 1024 threads) or 8
+// waves of a CU at once: with the usual 4-wave workgroups the gather refilled
+// each CU's wave slots as they freed and the first FD stage waited for it
+// (58 -> 162 us at 4096^2 FP32).  Workgroups of 1024 threads free 16 slots at a
+// time, which the dispatcher shares with the FD stage's.
 template <typename T, bool STREAM>
 void launch_gather_g(const KParams<T>& K, int par, long long n, hipStream_t st, const T* Ag,
                      T* praw, T* jx, T* jy) {
+  constexpr int NTB = 1024;
+  const unsigned grid = (unsigned)((n + NTB - 1) / NTB);
   if (par == 0)
-    k_gather<T, 0, true, STREAM, true><<<blocks1d(n), 256, 0, st>>>(K, nullptr, Ag, nullptr, praw, jx,
-                                                                   jy, nullptr, nullptr, nullptr);
+    k_gather<T, 0, true, STREAM, true, NTB><<<grid, NTB, 0, st>>>(K, nullptr, Ag, nullptr, praw,
+                                                                  jx, jy, nullptr, nullptr, nullptr);
   else
-    k_gather<T, 1, true, STREAM, true><<<blocks1d(n), 256, 0, st>>>(K, nullptr, Ag, nullptr, praw, jx,
-                                                                   jy, nullptr, nullptr, nullptr);
+    k_gather<T, 1, true, STREAM, true, NTB><<<grid, NTB, 0, st>>>(K, nullptr, Ag, nullptr, praw,
+                                                                  jx, jy, nullptr, nullptr, nullptr);
 }
 
 template <typename T, bool COUPLED, bool STREAM>

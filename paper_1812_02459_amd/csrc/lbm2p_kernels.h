@@ -398,14 +398,15 @@ __device__ __forceinline__ void gather_node(const KParams<T>& P, const T* __rest
   }
 }
 
-template <typename T, int PAR, bool COUPLED, bool STREAM, bool SKIP_F = false>
-__global__ __launch_bounds__(256) void k_gather(KParams<T> P, const T* __restrict__ Af,
+// NTB threads a workgroup, one node each
+template <typename T, int PAR, bool COUPLED, bool STREAM, bool SKIP_F = false, int NTB = 256>
+__global__ __launch_bounds__(NTB) void k_gather(KParams<T> P, const T* __restrict__ Af,
                                                 const T* __restrict__ Ag, T* __restrict__ phibar,
                                                 T* __restrict__ praw, T* __restrict__ jx,
                                                 T* __restrict__ jy, T* __restrict__ m7,
                                                 T* __restrict__ m8, T* __restrict__ m1) {
   const long long n = (long long)P.nx * P.ny;
-  const long long id = (long long)blockIdx.x * 256 + threadIdx.x;
+  const long long id = (long long)blockIdx.x * NTB + threadIdx.x;
   if (id >= n) return;
   const int y = (int)(id / P.nx), x = (int)(id - (long long)y * P.nx);
   gather_node<T, PAR, COUPLED, STREAM, SKIP_F>(P, Af, Ag, phibar, praw, jx, jy, m7, m8, m1, x, y,
